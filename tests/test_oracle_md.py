@@ -1,0 +1,138 @@
+"""Pins of the oracle's molecular dynamics (Example section: time step,
+thermostat, neighbour list updated at half the skin).
+
+Pinned by: the FCC/Maxwell-Boltzmann start (lattice distances, zero total
+momentum, exact kinetic temperature), the Verlet-list path being
+bit-identical to the all-pairs definition, second-order energy conservation
+of the gamma = 0 (velocity-Verlet) limit, the exact Ornstein-Uhlenbeck
+variance of the O step, and equipartition under the Langevin thermostat.
+"""
+import numpy as np
+import pytest
+
+RC = 2.5
+
+
+def test_init_fcc_and_velocities(orc):
+    for N, rho in [(256, 0.8442), (500, 0.8442), (300, 0.75), (1000, 0.9)]:
+        L = orc.box_length(N, rho)
+        T = 1.3
+        x, v = orc.init_replica(N, L, T, 1, 3)
+        # positions inside the box, minimum spacing of the FCC lattice
+        assert np.all(x >= -L / 2) and np.all(x < L / 2)
+        n = orc.fcc_cells if hasattr(orc, "fcc_cells") else None
+        ncell = int(np.ceil((N / 4) ** (1 / 3) - 1e-9))
+        while 4 * ncell**3 < N:
+            ncell += 1
+        a = L / ncell
+        d = x[:, None, :] - x[None, :, :]
+        d -= L * np.round(d / L)
+        r = np.sqrt((d * d).sum(-1)) + np.eye(N) * 1e9
+        assert r.min() == pytest.approx(a / np.sqrt(2), rel=1e-12)
+        # zero total momentum, exact temperature with 3N-3 degrees of freedom
+        assert np.abs(v.sum(0)).max() < 1e-10
+        assert (v * v).sum() == pytest.approx((3 * N - 3) * T, rel=1e-12)
+
+
+def test_box_length(orc):
+    for N, rho in [(256, 0.8442), (4000, 0.8442), (32000, 0.8442), (108000, 0.8442), (777, 0.71)]:
+        L = orc.box_length(N, rho)
+        assert (L * 4096) == int(L * 4096)
+        assert abs(L - (N / rho) ** (1 / 3)) <= 2.0**-13 + 1e-15
+
+
+def test_list_equals_all_pairs(orc):
+    """The Verlet-list run gives bit-identical trajectories to the run that
+    evaluates every pair each step; several list updates happen."""
+    N, rho, T = 256, 0.8442, 1.5
+    L = orc.box_length(N, rho)
+    x, v = orc.init_replica(N, L, T, 1, 0)
+    a = orc.Replica(x, v, L, RC)
+    b = orc.Replica(x, v, L, RC)
+    orc.md(a, 300, 0.3, 0.005, 1.0, T, 1, 0, use_list=True)
+    orc.md(b, 300, 0.3, 0.005, 1.0, T, 1, 0, use_list=False)
+    assert a.rebuilds >= 5
+    assert a.rebuilds == b.rebuilds
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v) and a.U == b.U
+
+
+def test_chunked_run_equals_single_run(orc):
+    N, T = 108, 1.0
+    L = orc.box_length(N, 0.8442)
+    x, v = orc.init_replica(N, L, T, 1, 2)
+    a = orc.Replica(x, v, L, RC)
+    b = orc.Replica(x, v, L, RC)
+    orc.md(a, 120, 0.3, 0.005, 1.0, T, 9, 2)
+    for n in (7, 50, 1, 62):
+        orc.md(b, n, 0.3, 0.005, 1.0, T, 9, 2)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.v, b.v) and a.rebuilds == b.rebuilds
+
+
+def nve_fluctuation(orc, dt, tmax, x, v, L):
+    rep = orc.Replica(x, v, L, RC)
+    steps = int(round(tmax / dt))
+    every = max(1, int(round(0.05 / dt)))
+    E = []
+    for _ in range(steps // every):
+        orc.md(rep, every, 0.3, dt, 0.0, 1.0, 1, 0)
+        E.append(rep.U + 0.5 * (rep.v**2).sum())
+    E = np.array(E)
+    return E.std(), E
+
+
+def test_nve_energy_second_order(orc):
+    """gamma = 0 is velocity Verlet: the total-energy fluctuation scales as
+    dt^2 (halving dt divides it by ~4) and there is no drift."""
+    N = 108
+    L = orc.box_length(N, 0.8442)
+    x, v = orc.init_replica(N, L, 1.0, 1, 0)
+    # equilibrate into the liquid with the thermostat first
+    rep = orc.Replica(x, v, L, RC)
+    orc.md(rep, 1500, 0.3, 0.004, 1.0, 1.0, 1, 0)
+    s1, E1 = nve_fluctuation(orc, 0.004, 4.0, rep.x, rep.v, L)
+    s2, E2 = nve_fluctuation(orc, 0.002, 4.0, rep.x, rep.v, L)
+    ratio = s1 / s2
+    assert 3.0 < ratio < 5.3, ratio
+    # no systematic drift beyond the fluctuation (force truncation at r_c
+    # makes a tiny random-walk contribution only)
+    assert abs(E1[-1] - E1[0]) < 10 * s1 + 1e-3 * abs(E1[0])
+
+
+def test_ostep_exact_variance(orc):
+    """With no interactions (r_c tiny) the velocities are an Ornstein-
+    Uhlenbeck process: after s steps from v0, <v> = c1^s v0 and
+    var = T (1 - c1^(2s)) exactly."""
+    N = 4000
+    L = 60.0
+    rng = np.random.default_rng(0)
+    x = rng.uniform(-L / 2, L / 2, (N, 3))
+    v0 = np.full((N, 3), 2.0)
+    rep = orc.Replica(x, v0, L, 1e-3)
+    gamma, dt, T, s = 1.0, 0.01, 0.8, 50
+    orc.md(rep, s, 0.3, dt, gamma, T, 5, 1)
+    c1s = np.exp(-gamma * dt * s)
+    v = rep.v.reshape(-1)
+    n = v.size
+    var = T * (1 - c1s**2)
+    assert v.mean() == pytest.approx(2.0 * c1s, abs=4 * np.sqrt(var / n))
+    assert v.var() == pytest.approx(var, rel=4 * np.sqrt(2.0 / n))
+
+
+@pytest.mark.slow
+def test_equipartition_langevin(orc):
+    """<2K/(3N)> = T under the Langevin thermostat (gamma = 1) in the LJ
+    liquid, within 4 sigma of block averages."""
+    N, T = 108, 1.2
+    L = orc.box_length(N, 0.8442)
+    x, v = orc.init_replica(N, L, T, 1, 0)
+    rep = orc.Replica(x, v, L, RC)
+    orc.md(rep, 1000, 0.3, 0.005, 1.0, T, 1, 0)
+    tk = []
+    for _ in range(3000):
+        orc.md(rep, 5, 0.3, 0.005, 1.0, T, 1, 0)
+        tk.append((rep.v**2).sum() / (3 * N))
+    tk = np.array(tk)
+    blocks = tk.reshape(30, -1).mean(1)
+    sem = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    # BAOAB's kinetic temperature carries an O(dt^2) bias, far below sem here
+    assert abs(tk.mean() - T) < 4 * sem + 2e-3, (tk.mean(), sem)
