@@ -70,6 +70,9 @@ def lib():
         L.oracle_forces.argtypes = [C.c_int32, C.c_double, C.c_double, dp, dp,
                                     C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.oracle_forces.restype = C.c_int
+        L.oracle_force_on.argtypes = [C.c_int32, C.c_double, C.c_double, dp, C.c_int32, dp,
+                                      C.POINTER(C.c_double)]
+        L.oracle_force_on.restype = C.c_int
         L.oracle_md.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_uint64, C.c_int32, C.c_int64,
                                 C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_int64),
@@ -142,6 +145,15 @@ def forces(x, L, rc):
     W = C.c_double()
     lib().oracle_forces(N, float(L), float(rc), x, F, C.byref(U), C.byref(W))
     return F.reshape(N, 3), U.value, W.value
+
+
+def force_on(x, L, rc, i):
+    """Force on atom i and its pair-energy sum, by the all-pairs definition."""
+    x = np.ascontiguousarray(x, np.float64).reshape(-1)
+    F = np.zeros(3)
+    e = C.c_double()
+    lib().oracle_force_on(x.size // 3, float(L), float(rc), x, int(i), F, C.byref(e))
+    return F, e.value
 
 
 def metropolis(Ua, Ub, Tj, Tj1, u):

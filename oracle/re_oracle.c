@@ -278,6 +278,30 @@ int oracle_forces(int32_t N, double L, double rc, const double* x, double* F, do
     return 0;
 }
 
+/* Force on one atom i and its pair-energy sum e_i = sum_j u(r_ij) (so that
+ * U = e/2 summed over atoms): the definition restricted to one row, for
+ * checking sampled atoms of large systems.                                  */
+int oracle_force_on(int32_t N, double L, double rc, const double* x, int32_t i, double* Fi, double* ei)
+{
+    const double rc2 = rc * rc;
+    const double ushift = oracle_lj_shift(rc);
+    double f[3] = {0.0, 0.0, 0.0}, e = 0.0;
+    for (int j = 0; j < N; ++j) {
+        if (j == i) continue;
+        double d[3];
+        for (int k = 0; k < 3; ++k) d[k] = min_image(x[3 * i + k] - x[3 * j + k], L);
+        double r2 = d[0] * d[0] + d[1] * d[1] + d[2] * d[2];
+        if (r2 < rc2) {
+            double fr;
+            e += lj_pair(r2, ushift, &fr);
+            for (int k = 0; k < 3; ++k) f[k] += fr * d[k];
+        }
+    }
+    for (int k = 0; k < 3; ++k) Fi[k] = f[k];
+    *ei = e;
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Verlet neighbour list (Example section: pairs up to r_c + skin, updated
  * when one particle moved more than half the skin since the last update).
