@@ -1,0 +1,176 @@
+"""Benchmark: atom-steps/s of batched replica-exchange LJ MD on one MI355X.
+
+One "step" is one MD step of every replica (list-update test, neighbour-list
+rebuilds where triggered, LJ force, BAOAB integration) plus, every N_x steps,
+the temperature-exchange attempt with velocity rescaling.  The default
+workload is 32 replicas x 4000 LJ atoms (rho 0.8442, geometric ladder
+T = 0.7 .. 2.0, r_c 2.5, skin 0.3, dt 0.005, N_x 50), batched mixed
+precision; the plain per-replica FP64 form is timed beside it.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "atom-steps/s over all replicas (batched mixed vs plain FP64) at stated tol"
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+
+
+def pair_counts(x, L, rc, rl):
+    """Unique pairs with r < rc and with rc <= r < rl (minimum image), by
+    brute force in blocks (measurement of the algorithmic work)."""
+    n_c = n_s = 0
+    N = len(x)
+    for a in range(0, N, 512):
+        d = x[a:a + 512, None, :] - x[None, :, :]
+        d -= L * np.round(d / L)
+        r2 = (d * d).sum(-1)
+        idx = np.arange(a, min(N, a + 512))[:, None]
+        upper = np.arange(N)[None, :] > idx
+        n_c += int(((r2 < rc * rc) & upper).sum())
+        n_s += int(((r2 >= rc * rc) & (r2 < rl * rl) & upper).sum())
+    return n_c, n_s
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="lj-32x4000")
+    ap.add_argument("--engine", default=None, help="persistent | lockstep (default: the library default)")
+    ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build runs every replica on a single MI355X; "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_0812_1633_amd import re as R
+    from paper_0812_1633_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    cfg = W.expand(args.workload)
+    N, rho, T = cfg["N_list"], cfg["rho_list"], cfg["T_list"]
+    rc, skin, dt, Nx, seed = cfg["rc"], cfg["skin"], cfg["dt"], cfg["Nx"], cfg["seed"]
+    atoms = int(N.sum())
+    kw = dict(rho_per_replica=rho, gamma=cfg["gamma"])
+    if args.engine:
+        kw["engine"] = args.engine
+
+    # ---- batched mixed-precision form ------------------------------------
+    eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw)
+    eng.step(args.warmup)
+    steps0, reb0 = eng.query_steps()
+    torch.cuda.synchronize()
+    eng.profile(1)
+    t0 = time.perf_counter()
+    eng.step(args.steps)
+    eng.query_energies()  # synchronises the library stream
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    eng.profile(0)
+    k_ms, k_n = eng.query_kernel_time()
+    steps1, reb1 = eng.query_steps()
+    done = int(((steps1 - steps0) * N).sum())
+    value = done / (t1 - t0)
+    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    acc_att, acc_acc = eng.query_acceptance()
+
+    # tolerance check in the same run: forces of sampled atoms of two
+    # replicas against the oracle's all-pairs definition
+    import oracle
+    L = eng.query_box()
+    tol = {"force_normwise_max": 0.0, "energy_rel_max": 0.0}
+    counts = []
+    for r in (0, len(N) - 1):
+        x, _ = eng.get_state(r)
+        F, U = eng.compute_forces(r)
+        g = np.random.default_rng(r)
+        idx = g.choice(int(N[r]), size=min(64, int(N[r])), replace=False)
+        Fo = np.array([oracle.force_on(x, L[r], rc, int(i))[0] for i in idx])
+        rms = np.sqrt((Fo * Fo).sum(1).mean())
+        tol["force_normwise_max"] = max(tol["force_normwise_max"], float(np.abs(F[idx] - Fo).max() / rms))
+        counts.append(pair_counts(x, L[r], rc, rc + skin) + (int(N[r]),))
+    Uo = None
+    r = 0
+    x, _ = eng.get_state(r)
+    Fo_all, Uo, _ = oracle.forces(x, L[r], rc)
+    _, Ug = eng.compute_forces(r)
+    tol["energy_rel_max"] = abs(Ug - Uo) / abs(Uo)
+    ok = tol["force_normwise_max"] <= 1e-5 and tol["energy_rel_max"] <= 1e-5
+
+    # algorithmic flops of one fused force launch: 27 per unique in-cutoff
+    # pair and 9 per unique pair in the skin shell, per replica, scaled by N
+    flop_per_atom = np.mean([(27 * c + 9 * s) / n for c, s, n in counts])
+    flops_launch = flop_per_atom * atoms
+    achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
+                "kernel": "k_force<PMixed,fused>", "kernel_ms": k_ms, "launches_timed": k_n,
+                "flop_per_atom_step": float(flop_per_atom)}
+    eng.close()
+
+    # ---- plain per-replica FP64 form ---------------------------------------
+    plain = None
+    if args.plain_steps > 0:
+        ep = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="fp64", form="plain", **kw)
+        ep.step(min(args.plain_steps, 50))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ep.step(args.plain_steps)
+        ep.query_energies()
+        t1 = time.perf_counter()
+        pv = atoms * args.plain_steps / (t1 - t0)
+        plain = {"value": pv, "unit": "atom-steps/s", "ms_per_step": 1e3 * (t1 - t0) / args.plain_steps,
+                 "steps": args.plain_steps, "ratio_mixed_over_plain": value / pv}
+        ep.close()
+
+    # ---- CPU baseline: the oracle on a bounded sample ----------------------
+    cpu = None
+    if not args.no_cpu:
+        nthreads = oracle.num_threads()
+        ens = oracle.Ensemble(N, L, T, rc, skin, dt, cfg["gamma"], seed)
+        t0 = time.perf_counter()
+        ens.run_sync(2, 10**9)
+        t_probe = time.perf_counter() - t0
+        n_more = max(1, int(args.cpu_seconds / max(t_probe / 2, 1e-6)))
+        t0 = time.perf_counter()
+        ens.run_sync(n_more, 10**9)
+        t1 = time.perf_counter()
+        cpu = {"value": atoms * n_more / (t1 - t0), "unit": "atom-steps/s", "cores": nthreads, "kind": "oracle",
+               "sample": "%d steps of all %d replicas of %s from the FCC start (Verlet-list oracle, "
+                         "OpenMP over replicas)" % (n_more, len(N), args.workload)}
+
+    out = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "replicas": int(len(N)), "atoms": atoms,
+                      "atoms_per_replica": int(N[0]) if len(set(N.tolist())) == 1 else "uneven",
+                      "rho": float(rho[0]) if len(set(rho.tolist())) == 1 else "uneven",
+                      "T_ladder": [float(T[0]), float(T[-1])], "r_c": rc, "skin": skin, "dt": dt, "N_x": Nx,
+                      "precision": "FP32 pair arithmetic, 32-bit fixed-point positions, FP64 energies/exchange",
+                      "engine": args.engine or "default", "parallelism": "replicas batched on 1 GPU"},
+           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain,
+           "tolerance": dict(tol, passed=bool(ok)),
+           "exchange": {"attempts": int(acc_att.sum()), "accepted": int(acc_acc.sum())},
+           "rebuilds_per_replica_step": float((reb1 - reb0).sum() / max(1, (steps1 - steps0).sum()))}
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -195,6 +195,15 @@ int re_test_exchange(const double* U, const double* T, const int32_t* slot, int 
 int re_test_philox(const uint32_t* ctr, uint32_t key0, uint32_t key1, int n, uint32_t* out);
 int re_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int n, double* out);
 
+/* Measurement of the dominant kernel (the fused force + integrate launch of
+ * the batched lockstep engine; the persistent launch of the persistent
+ * engine), timed with HIP events on the context's stream.  re_profile(ctx, 1)
+ * opens a window (at most 4096 launches are timed), re_profile(ctx, 0) closes
+ * it; re_query_kernel_time gives the number of launches timed in the last
+ * window and their mean duration in milliseconds. */
+int re_profile(re_ctx* ctx, int enable);
+int re_query_kernel_time(re_ctx* ctx, double* mean_ms, int64_t* n);
+
 /* Free everything owned by the context (NULL is allowed). */
 void re_destroy(re_ctx* ctx);
 

@@ -42,6 +42,7 @@ struct re_ctx {
     std::vector<void*> allocs;
     int64_t total_slots = 0;
     int total_cells = 0;
+    int cells_max = 1;  // largest ncell^3 over the replicas
     // block tables: batched (XCD-interleaved over all replicas) and
     // contiguous (replica r at [start[r], start[r] + count[r]))
     BlockTable bt1{}, btF{}, ct1{}, ctF{};
@@ -52,6 +53,12 @@ struct re_ctx {
     int64_t step = 0;          // common step count (sync forms)
     int64_t next_attempt = 0;  // global attempt index
     int pending_alpha = 0;     // the next start kernel applies the exchange factor
+    // force-kernel timing with HIP events (re_profile)
+    bool prof = false;
+    std::vector<hipEvent_t> ev;  // pairs
+    int ev_used = 0;
+    double prof_ms = 0;
+    int64_t prof_n = 0;
     std::string err;
 };
 
@@ -238,9 +245,7 @@ static int refresh_replicas(re_ctx* c, int r0, int nrep)
     for (int r = r0; r < r0 + nrep; ++r) {
         a.r0 = r;
         HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-        a.tab = c->ct1;
-        a.blk_off = c->c1_start[r];
-        HIPCHK(c, launch_listbuild(f64, c->d, a, c->c1_count[r], c->stream));
+        HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->cells_max, c->stream));
         a.tab = c->ctF;
         a.blk_off = c->cF_start[r];
         HIPCHK(c, launch_force(f64, kRefresh, c->d, a, c->cF_count[r], c->stream));
@@ -379,9 +384,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
             for (int r = 0; r < R; ++r) {
                 a.r0 = r;
                 HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-                a.tab = c->ct1;
-                a.blk_off = c->c1_start[r];
-                HIPCHK(c, launch_listbuild(f64, c->d, a, c->c1_count[r], c->stream));
+                HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->cells_max, c->stream));
                 a.tab = c->ctF;
                 a.blk_off = c->cF_start[r];
                 HIPCHK(c, launch_force(f64, mode, c->d, a, c->cF_count[r], c->stream));
@@ -390,11 +393,16 @@ static int run_lockstep(re_ctx* c, int64_t n)
         } else {
             a.r0 = 0;
             HIPCHK(c, launch_reorder(f64, c->d, a, R, c->stream));
+            HIPCHK(c, launch_listbuild(f64, c->d, a, R, c->cells_max, c->stream));
             a.blk_off = 0;
-            a.tab = c->bt1;
-            HIPCHK(c, launch_listbuild(f64, c->d, a, c->nbt1, c->stream));
             a.tab = c->btF;
+            const bool timed = c->prof && mode == kFused && c->ev_used + 2 <= (int)c->ev.size();
+            if (timed) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
             HIPCHK(c, launch_force(f64, mode, c->d, a, c->nbtF, c->stream));
+            if (timed) {
+                HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+                c->ev_used += 2;
+            }
             if (mode == kStopEnergy) HIPCHK(c, launch_energy(f64, c->d, a, R, c->stream));
         }
         if (stop) {
@@ -523,6 +531,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         rd.ncell = nc;
         rd.cell_base = cells;
         cells += nc * nc * nc + 1;
+        c->cells_max = std::max(c->cells_max, nc * nc * nc);
         rd.nl_base = nl;
         nl += (int64_t)rd.Np * c->cfg.M;
         if (c->prec == RE_MIXED) {
@@ -916,10 +925,49 @@ int re_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int n, double*
     return RE_OK;
 }
 
+// Timing of the dominant kernel (the fused force + integrate launch) with
+// HIP events on the context's stream.  enable = 1 starts a window (up to
+// 4096 launches are timed), 0 ends it; re_query_kernel_time reports the
+// launches timed in the last window and their mean duration.
+int re_profile(re_ctx* c, int enable)
+{
+    if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
+    if (enable) {
+        if (c->ev.empty()) {
+            c->ev.resize(2 * 4096);
+            for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+        }
+        c->ev_used = 0;
+        c->prof = true;
+        return RE_OK;
+    }
+    c->prof = false;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double tot = 0;
+    for (int i = 0; i + 1 < c->ev_used; i += 2) {
+        float ms = 0;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev[i], c->ev[i + 1]));
+        tot += ms;
+    }
+    c->prof_ms = tot;
+    c->prof_n = c->ev_used / 2;
+    c->ev_used = 0;
+    return RE_OK;
+}
+
+int re_query_kernel_time(re_ctx* c, double* mean_ms, int64_t* n)
+{
+    if (!c || !mean_ms || !n) return fail(c, RE_EINVAL, "NULL argument");
+    *n = c->prof_n;
+    *mean_ms = c->prof_n ? c->prof_ms / (double)c->prof_n : 0.0;
+    return RE_OK;
+}
+
 void re_destroy(re_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
+    for (auto e : c->ev) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

@@ -130,7 +130,8 @@ enum StepMode { kFused = 0, kStop = 1, kStopEnergy = 2, kQuery = 3, kRefresh = 4
 
 hipError_t launch_start(bool fp64, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
-hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
+hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int cells_max,
+                            hipStream_t st);
 hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,

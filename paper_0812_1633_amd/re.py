@@ -76,6 +76,8 @@ def lib():
         L.re_test_exchange.argtypes = [vp, vp, vp, C.c_int, u64, i64, vp]
         L.re_test_philox.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int, vp]
         L.re_test_normals.argtypes = [C.c_int, u64, vp, C.c_int, vp]
+        L.re_profile.argtypes = [vp, C.c_int]
+        L.re_query_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.re_destroy.argtypes = [vp]
         L.re_destroy.restype = None
         L.re_last_error.argtypes = [vp]
@@ -83,7 +85,8 @@ def lib():
         for f in ("re_create", "re_step", "re_exchange", "re_query_energies", "re_query_temps",
                   "re_query_slots", "re_query_box", "re_query_acceptance", "re_query_steps",
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
-                  "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals"):
+                  "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
+                  "re_profile", "re_query_kernel_time"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -221,8 +224,21 @@ class Engine:
                                            C.byref(tot)), self._ctx)
         return [buf[i] for i in range(n.value)], tot.value
 
+    def _n(self, r):
+        # out-of-range replicas reach the library, which rejects them
+        return int(self.N[r]) if 0 <= r < self.R else 0
+
+    def profile(self, enable):
+        _check(lib().re_profile(self._ctx, int(enable)), self._ctx)
+
+    def query_kernel_time(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        _check(lib().re_query_kernel_time(self._ctx, C.byref(ms), C.byref(n)), self._ctx)
+        return ms.value, n.value
+
     def get_state(self, r):
-        n = int(self.N[r])
+        n = self._n(r)
         x = np.zeros((n, 3))
         v = np.zeros((n, 3))
         _check(lib().re_get_state(self._ctx, int(r), _ptr(x), _ptr(v)), self._ctx)
@@ -231,11 +247,12 @@ class Engine:
     def set_state(self, r, x, v):
         x = np.ascontiguousarray(x, np.float64)
         v = np.ascontiguousarray(v, np.float64)
-        assert x.size == 3 * self.N[r] and v.size == 3 * self.N[r]
+        if x.size != 3 * self._n(r) or v.size != 3 * self._n(r):
+            raise ReError(RE_EINVAL, "x and v need 3 N values for replica %d" % r)
         _check(lib().re_set_state(self._ctx, int(r), _ptr(x), _ptr(v)), self._ctx)
 
     def compute_forces(self, r):
-        n = int(self.N[r])
+        n = self._n(r)
         F = np.zeros((n, 3))
         U = np.zeros(1)
         _check(lib().re_compute_forces(self._ctx, int(r), _ptr(F), _ptr(U)), self._ctx)
