@@ -43,6 +43,7 @@ struct re_ctx {
     int64_t total_slots = 0;
     int total_cells = 0;
     int cells_max = 1;  // largest ncell^3 over the replicas
+    int nmax = 0;       // largest replica
     // block tables: batched (XCD-interleaved over all replicas) and
     // contiguous (replica r at [start[r], start[r] + count[r]))
     BlockTable bt1{}, btF{}, ct1{}, ctF{};
@@ -245,7 +246,7 @@ static int refresh_replicas(re_ctx* c, int r0, int nrep)
     for (int r = r0; r < r0 + nrep; ++r) {
         a.r0 = r;
         HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-        HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->cells_max, c->stream));
+        HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->N[r], c->stream));
         a.tab = c->ctF;
         a.blk_off = c->cF_start[r];
         HIPCHK(c, launch_force(f64, kRefresh, c->d, a, c->cF_count[r], c->stream));
@@ -384,7 +385,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
             for (int r = 0; r < R; ++r) {
                 a.r0 = r;
                 HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-                HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->cells_max, c->stream));
+                HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->N[r], c->stream));
                 a.tab = c->ctF;
                 a.blk_off = c->cF_start[r];
                 HIPCHK(c, launch_force(f64, mode, c->d, a, c->cF_count[r], c->stream));
@@ -393,7 +394,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
         } else {
             a.r0 = 0;
             HIPCHK(c, launch_reorder(f64, c->d, a, R, c->stream));
-            HIPCHK(c, launch_listbuild(f64, c->d, a, R, c->cells_max, c->stream));
+            HIPCHK(c, launch_listbuild(f64, c->d, a, R, c->nmax, c->stream));
             a.blk_off = 0;
             a.tab = c->btF;
             const bool timed = c->prof && mode == kFused && c->ev_used + 2 <= (int)c->ev.size();
@@ -526,7 +527,9 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         rd.base = (int32_t)slots;
         slots += rd.Np;
         rd.L = c->L[r];
-        int nc = (int)std::floor(rd.L / (rlist * (1.0 + 1e-5)));
+        c->nmax = std::max(c->nmax, rd.N);
+        // fine cells: side >= r_list / 2 (the list build scans 5 x 5 x 5 cells)
+        int nc = (int)std::floor(rd.L / (0.5 * rlist * (1.0 + 1e-5)));
         nc = std::max(1, std::min(nc, kMaxCellsPerSide));
         rd.ncell = nc;
         rd.cell_base = cells;

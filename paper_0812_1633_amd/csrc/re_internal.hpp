@@ -7,7 +7,7 @@
 
 namespace re {
 
-constexpr int kMaxCellsPerSide = 20;               // cell grid cap (cells may exceed r_list)
+constexpr int kMaxCellsPerSide = 32;               // cell grid cap (cells may exceed r_list/2)
 constexpr int kMaxCells = kMaxCellsPerSide * kMaxCellsPerSide * kMaxCellsPerSide;
 constexpr int kReorderThreads = 1024;              // one workgroup per replica
 constexpr uint32_t kPurposeInitVel = 0u;           // Philox counter word 3 ("purpose")
@@ -130,8 +130,7 @@ enum StepMode { kFused = 0, kStop = 1, kStopEnergy = 2, kQuery = 3, kRefresh = 4
 
 hipError_t launch_start(bool fp64, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
-hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int cells_max,
-                            hipStream_t st);
+hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int nmax, hipStream_t st);
 hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,

@@ -271,55 +271,23 @@ __global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArg
     for (int c = tid; c <= ncc; c += nt) cstart[c] = cnt[c];
     for (int i = tid; i < rd.N; i += nt) perm[cnt[cellid[i]] + rank[i]] = i;
     __syncthreads();
-    // order every cell by atom id.  First the ids in cell order (into the
-    // free `cellid` scratch), then one wavefront per cell: an atom's place is
-    // the number of atoms of its cell with a smaller id, counted through lane
-    // shuffles 64 at a time; the next cell's ids are loaded while the
-    // current one is ranked.  The ordered slots go to `rank`.
+    // order every cell by atom id: the ids in cell order go to the free
+    // `cellid` scratch; each atom's place in its cell is the number of atoms
+    // of the cell with a smaller id.  The ordered slots go to `rank`.
     for (int k = tid; k < rd.N; k += nt) cellid[k] = P::id(pos[perm[k]]);
     __syncthreads();
-    {
-        const int lane = tid & 63, nw = nt >> 6;
-        int c = tid >> 6;
-        int a = 0, n = 0, id = 0x7fffffff, mine = 0;
-        if (c < ncc) {
-            a = cnt[c];
-            n = cnt[c + 1] - a;
-            id = lane < n ? cellid[a + lane] : 0x7fffffff;
-            mine = lane < n ? perm[a + lane] : 0;
+    for (int k = tid; k < rd.N; k += nt) {
+        // the cell of sorted slot k: binary search of the cell starts
+        int lo = 0, hi = ncc - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cnt[mid] <= k) lo = mid; else hi = mid - 1;
         }
-        while (c < ncc) {
-            const int c2 = c + nw;
-            int a2 = 0, n2 = 0, id2 = 0x7fffffff, mine2 = 0;
-            if (c2 < ncc) {
-                a2 = cnt[c2];
-                n2 = cnt[c2 + 1] - a2;
-                id2 = lane < n2 ? cellid[a2 + lane] : 0x7fffffff;
-                mine2 = lane < n2 ? perm[a2 + lane] : 0;
-            }
-            if (n <= 64) {
-                int rk = 0;
-                for (int l = 0; l < n; ++l) rk += __shfl(id, l) < id ? 1 : 0;
-                if (lane < n) rank[a + rk] = mine;
-            } else {
-                for (int bi = 0; bi < n; bi += 64) {
-                    const bool vi = bi + lane < n;
-                    const int m = vi ? perm[a + bi + lane] : 0;
-                    const int myid = vi ? cellid[a + bi + lane] : 0x7fffffff;
-                    int rk = 0;
-                    for (int bj = 0; bj < n; bj += 64) {
-                        const int jid = bj + lane < n ? cellid[a + bj + lane] : 0x7fffffff;
-                        for (int l = 0; l < 64; ++l) rk += __shfl(jid, l) < myid ? 1 : 0;
-                    }
-                    if (vi) rank[a + rk] = m;
-                }
-            }
-            c = c2;
-            a = a2;
-            n = n2;
-            id = id2;
-            mine = mine2;
-        }
+        const int a = cnt[lo], e = cnt[lo + 1];
+        const int myid = cellid[k];
+        int rk = 0;
+        for (int m = a; m < e; ++m) rk += cellid[m] < myid ? 1 : 0;
+        rank[a + rk] = perm[k];
     }
     __syncthreads();
     for (int k = tid; k < rd.N; k += nt) {
@@ -339,136 +307,108 @@ __global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArg
 }
 
 // ---------------------------------------------------------------------------
-// Cell-cooperative Verlet list build.  One workgroup per cell: the atoms of
-// the 27 neighbouring cells (every cell when there are fewer than 3 per side)
-// are staged in LDS, and each i-atom of the cell is tested against them by a
-// group of G lanes.  Pass 1 counts each lane's hits, a shuffle scan inside
-// the group gives each lane its first list entry, pass 2 writes the entries.
+// Verlet list build on the fine cell grid (cell side >= half the list
+// radius, cells ordered z fastest): the candidates of an atom are the atoms
+// of the 5 x 5 x 5 cells around its own, i.e. 25 rows of 5 consecutive
+// cells, each row one or two contiguous slot ranges of the cell-sorted
+// arrays (all cells when there are fewer than 5 per side).  A group of 32
+// lanes serves one atom, lane q scanning row q: it counts its hits and keeps
+// them as a bit mask, a shuffle scan over the group gives each lane its
+// first list entry, then the lane writes its hits.
 // Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa].
 template <class P>
-struct ListLds {
-    static constexpr int CH = P::kF64 ? 1024 : 2048;  // staged candidates per chunk
-    typename P::pos_t pos[CH];
-    int slot[CH];
-    int nb_start[28], nb_pre[28];
-    int nnb, total;
-};
-
-template <class P>
-__device__ void list_cell(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int c, int tpa,
-                          int M, ListLds<P>& sh)
+__device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int i,
+                                          bool act, int q, int tpa, int M)
 {
     using real = typename P::real;
-    constexpr int CH = ListLds<P>::CH;
-    const int t = threadIdx.x, nt = blockDim.x;
     const int nc = rd.ncell;
-    const int32_t* cstart = d.cell_start + rd.cell_base;
-    if (t == 0) {
-        int nnb = 0, tot = 0;
-        const int cz = c % nc, cy = (c / nc) % nc, cx = c / (nc * nc);
-        const int span = nc >= 3 ? 3 : nc;
-        for (int ox = 0; ox < span; ++ox)
-            for (int oy = 0; oy < span; ++oy)
-                for (int oz = 0; oz < span; ++oz) {
-                    const int x = nc >= 3 ? (cx + ox - 1 + nc) % nc : ox;
-                    const int y = nc >= 3 ? (cy + oy - 1 + nc) % nc : oy;
-                    const int z = nc >= 3 ? (cz + oz - 1 + nc) % nc : oz;
-                    const int q = (x * nc + y) * nc + z;
-                    sh.nb_start[nnb] = cstart[q];
-                    sh.nb_pre[nnb] = tot;
-                    tot += cstart[q + 1] - cstart[q];
-                    ++nnb;
+    const int32_t* cs = d.cell_start + rd.cell_base;
+    const typename P::pos_t pi = pos[act ? i : 0];
+    int s0 = 0, e0 = 0, s1 = 0, e1 = 0;
+    if (act) {
+        const int cx = P::cellc(pi.x, rd), cy = P::cellc(pi.y, rd), cz = P::cellc(pi.z, rd);
+        if (nc >= 5) {
+            if (q < 25) {
+                const int x = (cx + q / 5 - 2 + nc) % nc, y = (cy + q % 5 - 2 + nc) % nc;
+                const int rb = (x * nc + y) * nc;
+                const int z0 = cz - 2, z1 = cz + 2;
+                if (z0 < 0) {
+                    s0 = cs[rb + z0 + nc];
+                    e0 = cs[rb + nc];
+                    s1 = cs[rb];
+                    e1 = cs[rb + z1 + 1];
+                } else if (z1 >= nc) {
+                    s0 = cs[rb + z0];
+                    e0 = cs[rb + nc];
+                    s1 = cs[rb];
+                    e1 = cs[rb + z1 - nc + 1];
+                } else {
+                    s0 = cs[rb + z0];
+                    e0 = cs[rb + z1 + 1];
                 }
-        sh.nb_pre[nnb] = tot;
-        sh.nnb = nnb;
-        sh.total = tot;
+            }
+        } else if (q < nc * nc) {
+            s0 = cs[q * nc];
+            e0 = cs[q * nc + nc];
+        }
     }
-    __syncthreads();
-    const int total = sh.total;
-    const int ai = cstart[c], ni = cstart[c + 1] - ai;
     const real rl2 = P::rl2(rd);
-    const size_t Np = (size_t)rd.Np;
-    uint32_t* nl = d.nl + rd.nl_base;
-    const int nchunk = (total + CH - 1) / CH;
-    auto stage = [&](int c0) {
-        const int n = min(CH, total - c0);
-        for (int k = t; k < n; k += nt) {
-            const int g = c0 + k;
-            int b = 0;
-            while (sh.nb_pre[b + 1] <= g) ++b;
-            const int sl = sh.nb_start[b] + (g - sh.nb_pre[b]);
-            sh.pos[k] = pos[sl];
-            sh.slot[k] = sl;
-        }
-    };
-    for (int i0 = 0; i0 < ni; i0 += nt) {
-        const int nic = min(nt, ni - i0);
-        int G = 1;
-        while (G < 64 && 2 * G * nic <= nt) G <<= 1;
-        const int il = t / G, q = t % G;
-        const bool act = il < nic;
-        const int islot = ai + i0 + (act ? il : 0);
-        const typename P::pos_t pi = pos[islot];
-        int cnt = 0;
-        for (int ch = 0; ch < nchunk; ++ch) {
-            if (nchunk > 1 || i0 == 0) {
-                __syncthreads();
-                stage(ch * CH);
-                __syncthreads();
-            }
-            const int n = min(CH, total - ch * CH);
-            if (act)
-                for (int k = q; k < n; k += G) {
-                    real dx, dy, dz;
-                    P::diff(pi, sh.pos[k], rd, dx, dy, dz);
-                    cnt += (dx * dx + dy * dy + dz * dz < rl2 && sh.slot[k] != islot) ? 1 : 0;
-                }
-        }
-        // exclusive scan of the counts inside the group of G lanes
-        int off = cnt;
-        for (int m = 1; m < G; m <<= 1) {
-            const int v = __shfl_up(off, m, G);
-            if (q >= m) off += v;
-        }
-        const int tot_i = __shfl(off, G - 1, G);
-        off -= cnt;
-        for (int ch = 0; ch < nchunk; ++ch) {
-            if (nchunk > 1) {
-                __syncthreads();
-                stage(ch * CH);
-                __syncthreads();
-            }
-            const int n = min(CH, total - ch * CH);
-            if (act)
-                for (int k = q; k < n; k += G) {
-                    real dx, dy, dz;
-                    P::diff(pi, sh.pos[k], rd, dx, dy, dz);
-                    if (dx * dx + dy * dy + dz * dz < rl2 && sh.slot[k] != islot) {
-                        if (off < M) nl[((size_t)(off / tpa) * Np + islot) * tpa + (off % tpa)] = (uint32_t)sh.slot[k];
-                        ++off;
-                    }
-                }
-        }
-        if (act && q == 0) {
-            d.nn[rd.base + islot] = tot_i < M ? tot_i : M;
-            if (tot_i > M) atomicOr(d.overflow, 1u);
+    const int n0 = e0 - s0, len = n0 + (e1 - s1);
+    uint64_t mask = 0;
+    int cnt = 0;
+    for (int k = 0; k < len; ++k) {
+        const int j = k < n0 ? s0 + k : s1 + (k - n0);
+        real dx, dy, dz;
+        P::diff(pi, pos[j], rd, dx, dy, dz);
+        if (dx * dx + dy * dy + dz * dz < rl2 && j != i) {
+            if (k < 64) mask |= 1ull << k;
+            ++cnt;
         }
     }
-    __syncthreads();
+    int off = cnt;
+    for (int m = 1; m < 32; m <<= 1) {
+        const int v = __shfl_up(off, m, 32);
+        if (q >= m) off += v;
+    }
+    const int tot = __shfl(off, 31, 32);
+    off -= cnt;
+    uint32_t* nl = d.nl + rd.nl_base;
+    const size_t Np = (size_t)rd.Np;
+    auto put = [&](int j) {
+        if (off < M) nl[((size_t)(off / tpa) * Np + i) * tpa + (off % tpa)] = (uint32_t)j;
+        ++off;
+    };
+    if (len <= 64) {
+        while (mask) {
+            const int k = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            put(k < n0 ? s0 + k : s1 + (k - n0));
+        }
+    } else {
+        for (int k = 0; k < len; ++k) {
+            const int j = k < n0 ? s0 + k : s1 + (k - n0);
+            real dx, dy, dz;
+            P::diff(pi, pos[j], rd, dx, dy, dz);
+            if (dx * dx + dy * dy + dz * dz < rl2 && j != i) put(j);
+        }
+    }
+    if (act && q == 0) {
+        d.nn[rd.base + i] = tot < M ? tot : M;
+        if (tot > M) atomicOr(d.overflow, 1u);
+    }
 }
 
-// Lockstep wrapper: blockIdx.y = replica (from r0), blockIdx.x strides over
-// the replica's cells.
+// Lockstep wrapper: blockIdx.y = replica (from r0), 8 atoms per block.
 template <class P>
-__global__ __launch_bounds__(256) void k_listcell(DevState d, StepArgs sa)
+__global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
 {
     const int r = sa.r0 + blockIdx.y;
     if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
     const RepDev rd = d.rep[r];
-    __shared__ ListLds<P> sh;
+    const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
+    if (blockIdx.x * 8 >= rd.N) return;
     const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
-    const int ncc = rd.ncell * rd.ncell * rd.ncell;
-    for (int c = blockIdx.x; c < ncc; c += gridDim.x) list_cell<P>(d, rd, pos, c, sa.tpa, sa.M, sh);
+    list_rows<P>(d, rd, pos, i, i < rd.N, threadIdx.x & 31, sa.tpa, sa.M);
 }
 
 // ---------------------------------------------------------------------------
@@ -789,14 +729,14 @@ hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int 
     return hipGetLastError();
 }
 
-hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int cells_max, hipStream_t st)
+hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int nmax, hipStream_t st)
 {
     if (nrep <= 0) return hipSuccess;
-    const dim3 grid(cells_max < 64 ? cells_max : 64, nrep);
+    const dim3 grid((nmax + 7) / 8, nrep);
     if (fp64)
-        hipLaunchKernelGGL(k_listcell<PF64>, grid, dim3(256), 0, st, d, sa);
+        hipLaunchKernelGGL(k_listrows<PF64>, grid, dim3(256), 0, st, d, sa);
     else
-        hipLaunchKernelGGL(k_listcell<PMixed>, grid, dim3(256), 0, st, d, sa);
+        hipLaunchKernelGGL(k_listrows<PMixed>, grid, dim3(256), 0, st, d, sa);
     return hipGetLastError();
 }
 
