@@ -5,6 +5,7 @@
 // plain per-replica forms) and the persistent engine, and implements every
 // entry point of include/re.h.
 #include "re_internal.hpp"
+#include "re_persist.hpp"
 #include "../../include/re.h"
 
 #include <algorithm>
@@ -54,6 +55,22 @@ struct re_ctx {
     int64_t step = 0;          // common step count (sync forms)
     int64_t next_attempt = 0;  // global attempt index
     int pending_alpha = 0;     // the next start kernel applies the exchange factor
+    // persistent engine
+    bool pers_ok = false;        // a team plan fits the device
+    std::string pers_why;        // why not, when it does not
+    PersistState ps{};
+    CallParams* d_call = nullptr;
+    int64_t* d_target = nullptr;
+    int64_t* d_sched = nullptr;
+    int64_t sched_cap = 0;
+    std::vector<int64_t> sched;  // pending injected schedule (A x R)
+    int64_t sched_A = 0;
+    int32_t *t_rep = nullptr, *t_mem = nullptr, *t_size = nullptr, *t_id = nullptr;
+    unsigned* bar = nullptr;
+    int pnblk = 0, pnteams = 0;
+    std::vector<int> team_of;    // team size chosen per replica
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
     // force-kernel timing with HIP events (re_profile)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs
@@ -432,6 +449,189 @@ static int d2h(re_ctx* c, T* dst, const T* src, size_t n)
 }
 
 // ---------------------------------------------------------------------------
+// Persistent engine: team planning.  One 1024-thread workgroup per CU can be
+// resident (the reorder's cell counts fill most of the LDS), so at most
+// #CUs workgroups run.  Replica r gets a team of t_r workgroups in
+// proportion to its atoms (at least one, at most one per 256 atoms); a
+// team's workgroups are placed on one XCD when it fits (block ids of one
+// residue mod 8 go to the same XCD), so the replica's data stays in one L2.
+static int plan_persistent(re_ctx* c, int team_opt)
+{
+    int dev = 0, cus = 0, occ = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HIPCHK(c, persist_occupancy(c->prec == RE_FP64, c->cfg.tpa, &occ));
+    const int cap = cus * std::max(0, occ);
+    const int R = c->R;
+    c->pers_ok = false;
+    if (cap < R) {
+        c->pers_why = "the persistent engine needs one resident workgroup per replica (" + std::to_string(cap) +
+                      " available, " + std::to_string(R) + " replicas)";
+        return 0;
+    }
+    std::vector<int> t(R, 1);
+    if (team_opt > 0) {
+        for (int r = 0; r < R; ++r) t[r] = team_opt;
+    } else {
+        double tot = 0;
+        for (int r = 0; r < R; ++r) tot += c->N[r];
+        for (int r = 0; r < R; ++r) t[r] = std::max(1, (int)std::floor(cap * c->N[r] / tot));
+    }
+    for (int r = 0; r < R; ++r) t[r] = std::max(1, std::min(t[r], (c->N[r] + 255) / 256));
+    for (;;) {
+        int sum = 0, big = 0;
+        for (int r = 0; r < R; ++r) {
+            sum += t[r];
+            if (t[r] > t[big]) big = r;
+        }
+        if (sum <= cap) break;
+        t[big] -= 1;
+    }
+    // place teams: largest first, onto the XCD with the most free slots
+    const int X = 8, per = (cap + X - 1) / X;
+    std::vector<int> freec(X, per), order(R);
+    for (int r = 0; r < R; ++r) order[r] = r;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] > t[b]; });
+    std::vector<int32_t> brep(X * per, -1), bmem(X * per, 0), bsize(X * per, 1), bid(X * per, 0);
+    std::vector<int> used(X, 0);
+    for (int k = 0; k < R; ++k) {
+        const int r = order[k];
+        int x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
+        for (int m = 0; m < t[r]; ++m) {
+            if (freec[x] == 0) x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
+            const int b = x + X * used[x];
+            used[x] += 1;
+            freec[x] -= 1;
+            brep[b] = r;
+            bmem[b] = m;
+            bsize[b] = t[r];
+            bid[b] = r;
+        }
+    }
+    int nblk = 0;
+    for (int b = 0; b < X * per; ++b)
+        if (brep[b] >= 0) nblk = b + 1;
+    if (nblk > cap) {
+        c->pers_why = "team placement exceeds the resident workgroups";
+        return 0;
+    }
+    int rc;
+    if (!c->t_rep) {
+        if ((rc = dalloc(c, &c->t_rep, X * per)) || (rc = dalloc(c, &c->t_mem, X * per)) ||
+            (rc = dalloc(c, &c->t_size, X * per)) || (rc = dalloc(c, &c->t_id, X * per)) ||
+            (rc = dalloc(c, &c->bar, 64 * (size_t)R)))
+            return rc;
+    }
+    HIPCHK(c, hipMemcpy(c->t_rep, brep.data(), brep.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->t_mem, bmem.data(), bmem.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->t_size, bsize.data(), bsize.size() * 4, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->t_id, bid.data(), bid.size() * 4, hipMemcpyHostToDevice));
+    c->pnblk = nblk;
+    c->pnteams = R;
+    c->team_of = t;
+    c->pers_ok = true;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        (void)hipGraphDestroy(c->graph);
+        c->gexec = nullptr;
+        c->graph = nullptr;
+    }
+    return 0;
+}
+
+static PersistArgs persist_args(re_ctx* c)
+{
+    PersistArgs pa{};
+    pa.sa = base_args(c);
+    pa.st = c->ps;
+    pa.call = c->d_call;
+    pa.team_rep = c->t_rep;
+    pa.team_mem = c->t_mem;
+    pa.team_size = c->t_size;
+    pa.team_id = c->t_id;
+    pa.bar = c->bar;
+    pa.Nx = c->Nx;
+    pa.c1sq = c->c1 * c->c1;
+    pa.log_cap = c->cfg.log_cap;
+    pa.timeout = (uint64_t)(c->watchdog * 1e8);
+    return pa;
+}
+
+// One persistent launch (captured once into a HIP graph of the per-call
+// reset kernel and the persistent kernel, replayed for every call; the
+// per-call parameters live in device memory and are copied before).
+static int run_persistent(re_ctx* c, int64_t n)
+{
+    if (!c->pers_ok) return fail(c, RE_ESTATE, "%s", c->pers_why.c_str());
+    const int R = c->R;
+    std::vector<int64_t> steps(R);
+    int rc = d2h(c, steps.data(), c->d.steps, R);
+    if (rc) return rc;
+    CallParams cp{};
+    cp.cur0 = c->cur;
+    cp.k0 = c->next_attempt;
+    cp.target = c->d_target;
+    cp.sched = c->d_sched;
+    std::vector<int64_t> tgt(R);
+    if (!c->sched.empty()) {
+        cp.mode = kModeSchedule;
+        cp.A = c->sched_A;
+        if (c->sched_cap < (int64_t)c->sched.size()) {
+            if ((rc = dalloc(c, &c->d_sched, c->sched.size()))) return rc;
+            c->sched_cap = (int64_t)c->sched.size();
+            cp.sched = c->d_sched;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->d_sched, c->sched.data(), c->sched.size() * 8, hipMemcpyHostToDevice, c->stream));
+        for (int r = 0; r < R; ++r) tgt[r] = c->sched[(size_t)(c->sched_A - 1) * R + r];
+    } else {
+        cp.mode = c->xmode == RE_ASYNC ? kModeAsync : kModeSync;
+        cp.A = 0;
+        for (int r = 0; r < R; ++r) tgt[r] = steps[r] + n;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d_target, tgt.data(), R * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_call, &cp, sizeof cp, hipMemcpyHostToDevice, c->stream));
+    const bool f64 = c->prec == RE_FP64;
+    if (!c->gexec) {
+        const PersistArgs pa = persist_args(c);
+        hipStream_t cs;
+        HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) e = launch_persist(f64, c->d, pa, c->pnblk, c->pnteams, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e2 = hipStreamEndCapture(cs, &g);
+        if (e == hipSuccess) e = e2;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipStreamDestroy(cs);
+        if (e != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            c->gexec = nullptr;
+            return fail(c, RE_EDEVICE, "capturing the persistent launch: %s", hipGetErrorString(e));
+        }
+        c->graph = g;
+    }
+    const bool timed = c->prof && c->ev_used + 2 <= (int)c->ev.size();
+    if (timed) HIPCHK(c, hipEventRecord(c->ev[c->ev_used], c->stream));
+    HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    if (timed) {
+        HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
+        c->ev_used += 2;
+    }
+    uint32_t err = 0;
+    HIPCHK(c, hipMemcpyAsync(&err, c->ps.err, 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    std::vector<int64_t> katt(R);
+    if ((rc = d2h(c, katt.data(), c->ps.katt, R))) return rc;
+    c->next_attempt = *std::max_element(katt.begin(), katt.end());
+    if ((rc = d2h(c, steps.data(), c->d.steps, R))) return rc;
+    c->step = steps[0];
+    c->sched.clear();
+    c->sched_A = 0;
+    if (err & kErrTimeout)
+        return fail(c, RE_ETIMEOUT, "a device-side wait made no progress for %.1f s; the run was aborted", c->watchdog);
+    return check_overflow(c);
+}
+
+// ---------------------------------------------------------------------------
 // C ABI
 extern "C" {
 
@@ -624,6 +824,22 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.log_count, 1);
     ALLOC(d.overflow, 1);
     ALLOC(d.fq, 4 * slots);
+    ALLOC(c->ps.slotbuf, 2 * R);
+    ALLOC(c->ps.post, R);
+    ALLOC(c->ps.upost, 2 * R);
+    ALLOC(c->ps.spost, 2 * R);
+    ALLOC(c->ps.apend, R);
+    ALLOC(c->ps.katt, R);
+    ALLOC(c->ps.jprev, R);
+    ALLOC(c->ps.ctl, 2 * R);
+    ALLOC(c->ps.xdone, 1);
+    ALLOC(c->ps.trig, 1);
+    ALLOC(c->ps.parked, 1);
+    ALLOC(c->ps.beat, 1);
+    ALLOC(c->ps.abort, 1);
+    ALLOC(c->ps.err, 1);
+    ALLOC(c->d_call, 1);
+    ALLOC(c->d_target, R);
 #undef ALLOC
     if ((rc = build_tables(c))) return bail(rc);
 
@@ -655,6 +871,11 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     cp(d.overflow, z32.data(), 4);
     cp(d.flag, z32.data(), 2 * R * 4);
     cp(d.nn, zs.data(), slots * 4);
+    cp(c->ps.post, z64.data(), R * 8);
+    cp(c->ps.apend, z32.data(), R * 4);
+    cp(c->ps.katt, z64.data(), R * 8);
+    cp(c->ps.jprev, z64.data(), R * 8);
+    cp(c->ps.err, z32.data(), 4);
     if (e != hipSuccess) {
         c->err = std::string("initial copies failed: ") + hipGetErrorString(e);
         return bail(RE_EDEVICE);
@@ -677,6 +898,11 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         }
     }
     if ((rc = refresh_replicas(c, 0, R)) || (rc = check_overflow(c))) return bail(rc);
+    if (c->form == RE_BATCHED && (rc = plan_persistent(c, o.team_size))) return bail(rc);
+    if (c->xmode == RE_ASYNC && !c->pers_ok) {
+        c->err = "asynchronous exchange needs the persistent engine: " + c->pers_why;
+        return bail(RE_EINVAL);
+    }
     *out = c;
     return RE_OK;
 }
@@ -685,8 +911,8 @@ int re_step(re_ctx* c, int64_t n)
 {
     if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
     if (n < 0) return fail(c, RE_EINVAL, "n must be >= 0");
-    if (n == 0) return RE_OK;
-    if (c->xmode == RE_ASYNC) return fail(c, RE_ESTATE, "asynchronous exchange needs the persistent engine");
+    if (n == 0 && c->sched.empty()) return RE_OK;
+    if (c->xmode == RE_ASYNC || (c->form == RE_BATCHED && c->engine == RE_PERSISTENT)) return run_persistent(c, n);
     return run_lockstep(c, n);
 }
 
@@ -858,7 +1084,22 @@ int re_set_schedule(re_ctx* c, const int64_t* join, int64_t A)
     if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
     if (c->xmode != RE_ASYNC) return fail(c, RE_ESTATE, "schedules apply to asynchronous mode only");
     if (A < 0 || (A > 0 && !join)) return fail(c, RE_EINVAL, "bad schedule");
-    return fail(c, RE_ESTATE, "asynchronous mode needs the persistent engine");
+    const int R = c->R;
+    std::vector<int64_t> steps(R);
+    int rc = d2h(c, steps.data(), c->d.steps, R);
+    if (rc) return rc;
+    // each replica's join steps must increase strictly (a replica checks for
+    // attempts after each of its steps)
+    for (int64_t a = 0; a < A; ++a)
+        for (int r = 0; r < R; ++r) {
+            const int64_t prev = a ? join[(a - 1) * R + r] : steps[r];
+            if (join[a * R + r] <= prev)
+                return fail(c, RE_EINVAL, "join step of replica %d in attempt %lld must exceed %lld", r, (long long)a,
+                            (long long)prev);
+        }
+    c->sched.assign(join, join + A * R);
+    c->sched_A = A;
+    return RE_OK;
 }
 
 int re_test_exchange(const double* U, const double* T, const int32_t* slot, int R, uint64_t seed, int64_t attempt,
@@ -971,6 +1212,8 @@ void re_destroy(re_ctx* c)
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     for (auto e : c->ev) (void)hipEventDestroy(e);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;

@@ -1,404 +1,37 @@
-// re_kernels.hip -- gfx950 kernels of the replica-exchange LJ engine.
-//
-// Two precision policies share one set of kernel templates:
-//   PMixed: positions are 32-bit periodic fixed point (one int32 per
-//           coordinate spans the box, so integer wraparound is the minimum
-//           image and the cell index is an exact integer product), pair
-//           vectors are converted to FP32 in grid units; velocities and
-//           forces FP32; the per-replica energy sum and all exchange
-//           arithmetic are FP64.
-//   PF64:   FP64 positions (explicit minimum image), velocities and forces.
-//
-// The step is BAOAB Langevin dynamics (velocity-Verlet core) on a Verlet
-// neighbour list to r_c + skin, updated when one atom moved more than
-// skin/2 since the last update (Example section).  Temperatures move
-// between replicas by the Metropolis rule (Implementation section).
-#include "re_internal.hpp"
+// re_kernels.hip -- lockstep kernels of the replica-exchange LJ engine:
+// one launch per phase for a batch of replicas (the batched lockstep form)
+// or for one replica (the plain per-replica form), plus the exchange kernel
+// and the test hooks.  The per-atom arithmetic lives in re_device.hpp.
+#include "re_device.hpp"
 
 namespace re {
 
-// ---------------------------------------------------------------------------
-// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
-// 32x32->64 multiplications by the Philox multipliers, the high halves mixed
-// with the odd counter words and the round key; the key advances by the two
-// Weyl constants between rounds.
-__device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int i = 0; i < 10; ++i) {
-        if (i) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x), lo0 = 0xD2511F53u * c.x;
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z), lo1 = 0xCD9E8D57u * c.z;
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
-    }
-    return c;
-}
-
-__device__ __forceinline__ uint4 draw(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3)
-{
-    return philox10(make_uint4(c0, c1, c2, c3), (uint32_t)seed, (uint32_t)(seed >> 32));
-}
-
-// Box-Muller (Box & Muller 1958): words 0,1 -> cos/sin pair, words 2,3 -> cos.
-// FP32 version takes the top 24 bits of each word: u = (w>>8 + 1/2) 2^-24.
-__device__ __forceinline__ void normals3f(uint4 w, float& z0, float& z1, float& z2)
-{
-    const float u0 = ((float)(w.x >> 8) + 0.5f) * 0x1p-24f;
-    const float u1 = ((float)(w.y >> 8) + 0.5f) * 0x1p-24f;
-    const float u2 = ((float)(w.z >> 8) + 0.5f) * 0x1p-24f;
-    const float u3 = ((float)(w.w >> 8) + 0.5f) * 0x1p-24f;
-    const float r01 = __fsqrt_rn(-2.0f * __logf(u0));
-    const float r23 = __fsqrt_rn(-2.0f * __logf(u2));
-    float s1, c1;
-    __sincosf(6.28318530717958648f * u1, &s1, &c1);
-    z0 = r01 * c1;
-    z1 = r01 * s1;
-    z2 = r23 * __cosf(6.28318530717958648f * u3);
-}
-
-// FP64 version: u = (w + 1/2) 2^-32.
-__device__ __forceinline__ void normals3d(uint4 w, double& z0, double& z1, double& z2)
-{
-    const double u0 = ((double)w.x + 0.5) * 0x1p-32;
-    const double u1 = ((double)w.y + 0.5) * 0x1p-32;
-    const double u2 = ((double)w.z + 0.5) * 0x1p-32;
-    const double u3 = ((double)w.w + 0.5) * 0x1p-32;
-    const double two_pi = 6.283185307179586476925286766559;
-    const double r01 = sqrt(-2.0 * log(u0));
-    const double r23 = sqrt(-2.0 * log(u2));
-    z0 = r01 * cos(two_pi * u1);
-    z1 = r01 * sin(two_pi * u1);
-    z2 = r23 * cos(two_pi * u3);
-}
-
-// 53-bit uniform of exchange attempt k for the lower replica id.
-__device__ __forceinline__ double uniform53(uint64_t seed, int64_t k, int32_t lower)
-{
-    const uint4 w = draw(seed, (uint32_t)(uint64_t)k, (uint32_t)((uint64_t)k >> 32), (uint32_t)lower, kPurposeExchange);
-    const uint64_t m = ((uint64_t)(w.x >> 5) << 26) | (uint64_t)(w.y >> 6);
-    return (double)m * 0x1p-53;
-}
-
-// ---------------------------------------------------------------------------
-// Precision policies.
-struct PMixed {
-    using pos_t = int4;
-    using vel_t = float4;
-    using real = float;
-    static constexpr bool kF64 = false;
-    __device__ static pos_t* pos(const DevState& d, int b) { return d.posi[b]; }
-    __device__ static vel_t* vel(const DevState& d) { return d.velf; }
-    __device__ static vel_t* velt(const DevState& d) { return d.veltf; }
-    __device__ static vel_t* frc(const DevState& d) { return d.frcf; }
-    __device__ static pos_t* xref(const DevState& d) { return d.xrefi; }
-    __device__ static real* epot(const DevState& d) { return d.epotf; }
-    __device__ static int id(const pos_t& p) { return p.w; }
-    __device__ static int wrapdiff(int a, int b) { return (int)((uint32_t)a - (uint32_t)b); }
-    // pair vector a - b in grid units (the wraparound is the minimum image)
-    __device__ static void diff(const pos_t& a, const pos_t& b, const RepDev&, real& dx, real& dy, real& dz)
-    {
-        dx = (float)wrapdiff(a.x, b.x);
-        dy = (float)wrapdiff(a.y, b.y);
-        dz = (float)wrapdiff(a.z, b.z);
-    }
-    // x += h v: the displacement rounded to the grid; wraps by itself
-    __device__ static pos_t drift(pos_t p, real hx, real hy, real hz, const RepDev& rd)
-    {
-        p.x = (int)((uint32_t)p.x + (uint32_t)__float2int_rn(hx * rd.inv_sf));
-        p.y = (int)((uint32_t)p.y + (uint32_t)__float2int_rn(hy * rd.inv_sf));
-        p.z = (int)((uint32_t)p.z + (uint32_t)__float2int_rn(hz * rd.inv_sf));
-        return p;
-    }
-    __device__ static int cellc(int x, const RepDev& rd)
-    {
-        return (int)__umulhi((uint32_t)x ^ 0x80000000u, (uint32_t)rd.ncell);
-    }
-    __device__ static real rc2(const RepDev& rd) { return rd.rc2f; }
-    __device__ static real rl2(const RepDev& rd) { return rd.rl2f; }
-    __device__ static real lim2(const RepDev& rd) { return rd.lim2f; }
-};
-
-struct PF64 {
-    using pos_t = double4;
-    using vel_t = double4;
-    using real = double;
-    static constexpr bool kF64 = true;
-    __device__ static pos_t* pos(const DevState& d, int b) { return d.posd[b]; }
-    __device__ static vel_t* vel(const DevState& d) { return d.veld; }
-    __device__ static vel_t* velt(const DevState& d) { return d.veltd; }
-    __device__ static vel_t* frc(const DevState& d) { return d.frcd; }
-    __device__ static pos_t* xref(const DevState& d) { return d.xrefd; }
-    __device__ static real* epot(const DevState& d) { return d.epotd; }
-    __device__ static int id(const pos_t& p) { return (int)p.w; }
-    __device__ static double mi(double x, const RepDev& rd) { return x - rd.L * rint(x / rd.L); }
-    __device__ static void diff(const pos_t& a, const pos_t& b, const RepDev& rd, real& dx, real& dy, real& dz)
-    {
-        dx = mi(a.x - b.x, rd);
-        dy = mi(a.y - b.y, rd);
-        dz = mi(a.z - b.z, rd);
-    }
-    __device__ static double wrap(double x, const RepDev& rd) { return x - rd.L * floor((x + 0.5 * rd.L) / rd.L); }
-    __device__ static pos_t drift(pos_t p, real hx, real hy, real hz, const RepDev& rd)
-    {
-        p.x = wrap(p.x + hx, rd);
-        p.y = wrap(p.y + hy, rd);
-        p.z = wrap(p.z + hz, rd);
-        return p;
-    }
-    __device__ static int cellc(double x, const RepDev& rd)
-    {
-        int c = (int)floor((x / rd.L + 0.5) * (double)rd.ncell);
-        return c < 0 ? 0 : (c >= rd.ncell ? rd.ncell - 1 : c);
-    }
-    __device__ static real rc2(const RepDev& rd) { return rd.rc2d; }
-    __device__ static real rl2(const RepDev& rd) { return rd.rl2d; }
-    __device__ static real lim2(const RepDev& rd) { return rd.lim2d; }
-};
-
-template <class P>
-__device__ __forceinline__ void set_xyz(typename P::vel_t& v, typename P::real x, typename P::real y, typename P::real z)
-{
-    v.x = x;
-    v.y = y;
-    v.z = z;
-}
-
-// ---------------------------------------------------------------------------
-// First half of a step from a stopped boundary (B A O A of BAOAB), for every
-// atom of the block's replica:  v = alpha v + h F;  x += h v;
-// v = c1 v + c2 xi;  x += h v;  then the half-skin test against xref.
 template <class P>
 __global__ __launch_bounds__(256) void k_start(DevState d, StepArgs sa)
 {
-    using real = typename P::real;
-    const int cur = sa.cur, R = sa.R;
-    const int64_t step = sa.step;
     const int b = sa.blk_off + blockIdx.x;
     const int r = sa.tab.rep[b];
     if (r < 0) return;
     const RepDev rd = d.rep[r];
     const int i = sa.tab.a0[b] + threadIdx.x;
     if (i >= rd.N) return;
-    const int g = rd.base + i;
-    typename P::pos_t* pos = P::pos(d, cur);
-    typename P::pos_t x = pos[g];
-    typename P::vel_t v = P::vel(d)[g];
-    const typename P::vel_t f = P::frc(d)[g];
-    const real hh = (real)sa.h;
-    const real a = sa.apply_alpha ? (real)d.alpha[r] : (real)1;
-    const real c1 = (real)sa.c1;
-    const real c2 = (real)d.c2[r];
-    real vx = a * v.x + hh * f.x, vy = a * v.y + hh * f.y, vz = a * v.z + hh * f.z;
-    x = P::drift(x, hh * vx, hh * vy, hh * vz, rd);
-    const uint4 w = draw(sa.seed, (uint32_t)P::id(x), (uint32_t)step, (uint32_t)r, kPurposeOStep);
-    real z0, z1, z2;
-    if constexpr (P::kF64) {
-        normals3d(w, z0, z1, z2);
-    } else {
-        normals3f(w, z0, z1, z2);
-    }
-    vx = c1 * vx + c2 * z0;
-    vy = c1 * vy + c2 * z1;
-    vz = c1 * vz + c2 * z2;
-    x = P::drift(x, hh * vx, hh * vy, hh * vz, rd);
-    pos[g] = x;
-    set_xyz<P>(v, vx, vy, vz);
-    P::vel(d)[g] = v;
-    real dx, dy, dz;
-    P::diff(x, P::xref(d)[g], rd, dx, dy, dz);
-    if (dx * dx + dy * dy + dz * dz > P::lim2(rd)) atomicOr(&d.flag[(size_t)((step + 1) & 1) * R + r], 1u);
+    start_atom<P>(d, sa, rd, r, i, sa.cur, sa.step, sa.apply_alpha != 0);
 }
 
-// ---------------------------------------------------------------------------
-// Reorder one replica by cell (one workgroup per replica): counting sort of
-// the atoms into the cell grid, each cell ordered by atom id so the result is
-// independent of scheduling; x_ref := x.  Runs only for replicas whose
-// update flag of this parity is set (or all, when force_all).
+// One workgroup per replica; runs only where the update flag of this parity
+// is set (or everywhere with force_all).
 template <class P>
 __global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArgs sa)
 {
-    const int cur = sa.cur, par = sa.par, R = sa.R, force_all = sa.force_all;
     const int r = sa.r0 + blockIdx.x;
-    if (!force_all && d.flag[(size_t)par * R + r] == 0) return;
-    const RepDev rd = d.rep[r];
+    if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
     __shared__ int cnt[kMaxCells + 1];
     __shared__ int part[kReorderThreads];
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int nc = rd.ncell, ncc = nc * nc * nc;
-    typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-    typename P::pos_t* tmp = P::pos(d, cur ^ 1) + rd.base;
-    typename P::vel_t* vel = P::vel(d) + rd.base;
-    typename P::vel_t* velt = P::velt(d) + rd.base;
-    int32_t* cellid = d.cellid + rd.base;
-    int32_t* rank = d.rank + rd.base;
-    int32_t* perm = d.perm + rd.base;
-    for (int c = tid; c < ncc; c += nt) cnt[c] = 0;
-    __syncthreads();
-    for (int i = tid; i < rd.N; i += nt) {
-        const typename P::pos_t p = pos[i];
-        const int c = (P::cellc(p.x, rd) * nc + P::cellc(p.y, rd)) * nc + P::cellc(p.z, rd);
-        cellid[i] = c;
-        rank[i] = atomicAdd(&cnt[c], 1);
-    }
-    __syncthreads();
-    // exclusive scan of the counts: contiguous chunks per thread, then a scan
-    // of the chunk sums
-    const int chunk = (ncc + nt - 1) / nt;
-    const int c0 = tid * chunk, c1 = min(ncc, c0 + chunk);
-    int s = 0;
-    for (int c = c0; c < c1; ++c) s += cnt[c];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < nt; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
-    }
-    int run = part[tid] - s;
-    for (int c = c0; c < c1; ++c) {
-        const int n = cnt[c];
-        cnt[c] = run;
-        run += n;
-    }
-    __syncthreads();
-    if (tid == 0) cnt[ncc] = rd.N;
-    __syncthreads();
-    int32_t* cstart = d.cell_start + rd.cell_base;
-    for (int c = tid; c <= ncc; c += nt) cstart[c] = cnt[c];
-    for (int i = tid; i < rd.N; i += nt) perm[cnt[cellid[i]] + rank[i]] = i;
-    __syncthreads();
-    // order every cell by atom id: the ids in cell order go to the free
-    // `cellid` scratch; each atom's place in its cell is the number of atoms
-    // of the cell with a smaller id.  The ordered slots go to `rank`.
-    for (int k = tid; k < rd.N; k += nt) cellid[k] = P::id(pos[perm[k]]);
-    __syncthreads();
-    for (int k = tid; k < rd.N; k += nt) {
-        // the cell of sorted slot k: binary search of the cell starts
-        int lo = 0, hi = ncc - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (cnt[mid] <= k) lo = mid; else hi = mid - 1;
-        }
-        const int a = cnt[lo], e = cnt[lo + 1];
-        const int myid = cellid[k];
-        int rk = 0;
-        for (int m = a; m < e; ++m) rk += cellid[m] < myid ? 1 : 0;
-        rank[a + rk] = perm[k];
-    }
-    __syncthreads();
-    for (int k = tid; k < rd.N; k += nt) {
-        const int src = rank[k];
-        tmp[k] = pos[src];
-        velt[k] = vel[src];
-    }
-    __syncthreads();
-    typename P::pos_t* xref = P::xref(d) + rd.base;
-    for (int k = tid; k < rd.N; k += nt) {
-        const typename P::pos_t p = tmp[k];
-        pos[k] = p;
-        xref[k] = p;
-        vel[k] = velt[k];
-    }
-    if (tid == 0) d.rebuilds[r] += 1;
+    const RepDev rd = d.rep[r];
+    reorder_replica<P>(d, rd, r, sa.cur, cnt, part);
 }
 
-// ---------------------------------------------------------------------------
-// Verlet list build on the fine cell grid (cell side >= half the list
-// radius, cells ordered z fastest): the candidates of an atom are the atoms
-// of the 5 x 5 x 5 cells around its own, i.e. 25 rows of 5 consecutive
-// cells, each row one or two contiguous slot ranges of the cell-sorted
-// arrays (all cells when there are fewer than 5 per side).  A group of 32
-// lanes serves one atom, lane q scanning row q: it counts its hits and keeps
-// them as a bit mask, a shuffle scan over the group gives each lane its
-// first list entry, then the lane writes its hits.
-// Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa].
-template <class P>
-__device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int i,
-                                          bool act, int q, int tpa, int M)
-{
-    using real = typename P::real;
-    const int nc = rd.ncell;
-    const int32_t* cs = d.cell_start + rd.cell_base;
-    const typename P::pos_t pi = pos[act ? i : 0];
-    int s0 = 0, e0 = 0, s1 = 0, e1 = 0;
-    if (act) {
-        const int cx = P::cellc(pi.x, rd), cy = P::cellc(pi.y, rd), cz = P::cellc(pi.z, rd);
-        if (nc >= 5) {
-            if (q < 25) {
-                const int x = (cx + q / 5 - 2 + nc) % nc, y = (cy + q % 5 - 2 + nc) % nc;
-                const int rb = (x * nc + y) * nc;
-                const int z0 = cz - 2, z1 = cz + 2;
-                if (z0 < 0) {
-                    s0 = cs[rb + z0 + nc];
-                    e0 = cs[rb + nc];
-                    s1 = cs[rb];
-                    e1 = cs[rb + z1 + 1];
-                } else if (z1 >= nc) {
-                    s0 = cs[rb + z0];
-                    e0 = cs[rb + nc];
-                    s1 = cs[rb];
-                    e1 = cs[rb + z1 - nc + 1];
-                } else {
-                    s0 = cs[rb + z0];
-                    e0 = cs[rb + z1 + 1];
-                }
-            }
-        } else if (q < nc * nc) {
-            s0 = cs[q * nc];
-            e0 = cs[q * nc + nc];
-        }
-    }
-    const real rl2 = P::rl2(rd);
-    const int n0 = e0 - s0, len = n0 + (e1 - s1);
-    uint64_t mask = 0;
-    int cnt = 0;
-    for (int k = 0; k < len; ++k) {
-        const int j = k < n0 ? s0 + k : s1 + (k - n0);
-        real dx, dy, dz;
-        P::diff(pi, pos[j], rd, dx, dy, dz);
-        if (dx * dx + dy * dy + dz * dz < rl2 && j != i) {
-            if (k < 64) mask |= 1ull << k;
-            ++cnt;
-        }
-    }
-    int off = cnt;
-    for (int m = 1; m < 32; m <<= 1) {
-        const int v = __shfl_up(off, m, 32);
-        if (q >= m) off += v;
-    }
-    const int tot = __shfl(off, 31, 32);
-    off -= cnt;
-    uint32_t* nl = d.nl + rd.nl_base;
-    const size_t Np = (size_t)rd.Np;
-    auto put = [&](int j) {
-        if (off < M) nl[((size_t)(off / tpa) * Np + i) * tpa + (off % tpa)] = (uint32_t)j;
-        ++off;
-    };
-    if (len <= 64) {
-        while (mask) {
-            const int k = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            put(k < n0 ? s0 + k : s1 + (k - n0));
-        }
-    } else {
-        for (int k = 0; k < len; ++k) {
-            const int j = k < n0 ? s0 + k : s1 + (k - n0);
-            real dx, dy, dz;
-            P::diff(pi, pos[j], rd, dx, dy, dz);
-            if (dx * dx + dy * dy + dz * dz < rl2 && j != i) put(j);
-        }
-    }
-    if (act && q == 0) {
-        d.nn[rd.base + i] = tot < M ? tot : M;
-        if (tot > M) atomicOr(d.overflow, 1u);
-    }
-}
-
-// Lockstep wrapper: blockIdx.y = replica (from r0), 8 atoms per block.
+// blockIdx.y = replica (from r0), 8 atoms (32 lanes each) per block.
 template <class P>
 __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
 {
@@ -411,170 +44,31 @@ __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
     list_rows<P>(d, rd, pos, i, i < rd.N, threadIdx.x & 31, sa.tpa, sa.M);
 }
 
-// ---------------------------------------------------------------------------
-// LJ force (+ energy) over the Verlet list, TPA lanes per atom, then the
-// step epilogue selected by MODE:
-//   kFused:      v += h F (ends this step), v += h F, x += h v, O, x += h v
-//                (the next step's first half; positions to the other buffer)
-//   kStop/kStopEnergy: v += h F; store F (and the per-atom energy)
-//   kQuery:      F and energy to the query buffer in atom-id order only
-//   kRefresh:    store F and the per-atom energy; velocities untouched.
-// u(r) = 4 (r^-12 - r^-6) - u(r_c), F_i = 24 (2 r^-14 - r^-8) r_ij for r < r_c
-// (Example section: cutoff 2.5; energy shifted, force truncated).
+// Force + epilogue; the first block of each replica also marks the list of
+// this parity consumed and the pending velocity factor applied.
 template <class P, int MODE, int TPA>
 __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
 {
-    using real = typename P::real;
-    constexpr bool kEnergy = (MODE == kStopEnergy || MODE == kQuery || MODE == kRefresh);
-    const int cur = sa.cur, par = sa.par, R = sa.R;
-    const int64_t step_next = sa.step;
     const int b = sa.blk_off + blockIdx.x;
     const int r = sa.tab.rep[b];
     if (r < 0) return;
     const RepDev rd = d.rep[r];
     const int a0 = sa.tab.a0[b];
-    if (MODE != kQuery && a0 == 0 && threadIdx.x == 0) d.flag[(size_t)par * R + r] = 0u;  // list consumed
+    if (MODE != kQuery && a0 == 0 && threadIdx.x == 0) {
+        d.flag[(size_t)sa.par * sa.R + r] = 0u;
+        d.alpha[r] = 1.0;
+    }
     const int ia = a0 + (int)(threadIdx.x / TPA);
-    const int q = (int)(threadIdx.x % TPA);
-    const bool valid = ia < rd.N;
-    const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-    real fx = 0, fy = 0, fz = 0, e = 0;
-    typename P::pos_t pi{};
-    if (valid) {
-        pi = pos[ia];
-        const int nnb = d.nn[rd.base + ia];
-        const uint32_t* __restrict__ nlp = d.nl + rd.nl_base + (size_t)ia * TPA + q;
-        const size_t stride = (size_t)rd.Np * TPA;
-        const int nrow = (nnb - q + TPA - 1) / TPA;
-        if constexpr (P::kF64) {
-            const double rc2 = rd.rc2d;
-            for (int kk = 0; kk < nrow; ++kk) {
-                const uint32_t j = nlp[(size_t)kk * stride];
-                double dx, dy, dz;
-                P::diff(pi, pos[j], rd, dx, dy, dz);
-                const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
-                    const double ir2 = 1.0 / r2;
-                    const double ir6 = ir2 * ir2 * ir2;
-                    const double ff = 24.0 * ir2 * ir6 * (2.0 * ir6 - 1.0);
-                    fx += ff * dx;
-                    fy += ff * dy;
-                    fz += ff * dz;
-                    if constexpr (kEnergy) e += 4.0 * ir6 * (ir6 - 1.0) - sa.ushiftd;
-                }
-            }
-        } else {
-            const float rc2 = rd.rc2f, lo = rd.near_lo, hi = rd.near_hi, is2 = rd.inv_s2f;
-            const float ushift = (float)sa.ushiftd;
-            const uint64_t thr = rd.rc2_exact;
-            for (int kk = 0; kk < nrow; ++kk) {
-                const uint32_t j = nlp[(size_t)kk * stride];
-                const int4 pj = pos[j];
-                const int ix = PMixed::wrapdiff(pi.x, pj.x);
-                const int iy = PMixed::wrapdiff(pi.y, pj.y);
-                const int iz = PMixed::wrapdiff(pi.z, pj.z);
-                const float dx = (float)ix, dy = (float)iy, dz = (float)iz;
-                const float r2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dx * dx));
-                bool in = r2 < rc2;
-                if (__builtin_expect(r2 > lo && r2 < hi, 0)) {
-                    // within 2^-20 of the cutoff: decide on the exact integer square
-                    const uint64_t e2 = (uint64_t)((int64_t)ix * ix) + (uint64_t)((int64_t)iy * iy) +
-                                        (uint64_t)((int64_t)iz * iz);
-                    in = e2 < thr;
-                }
-                const float ir2 = __builtin_amdgcn_rcpf(r2) * is2;
-                const float ir6 = ir2 * ir2 * ir2;
-                const float ff = in ? ir2 * ir6 * __builtin_fmaf(48.0f, ir6, -24.0f) : 0.0f;
-                fx = __builtin_fmaf(ff, dx, fx);
-                fy = __builtin_fmaf(ff, dy, fy);
-                fz = __builtin_fmaf(ff, dz, fz);
-                if constexpr (kEnergy) e += in ? __builtin_fmaf(4.0f * ir6, ir6, -4.0f * ir6) - ushift : 0.0f;
-            }
-        }
-    }
-#pragma unroll
-    for (int m = 1; m < TPA; m <<= 1) {
-        fx += __shfl_xor(fx, m, TPA);
-        fy += __shfl_xor(fy, m, TPA);
-        fz += __shfl_xor(fz, m, TPA);
-        if constexpr (kEnergy) e += __shfl_xor(e, m, TPA);
-    }
-    if (!valid || q != 0) return;
-    if constexpr (!P::kF64) {  // grid units -> LJ units
-        fx *= rd.sf;
-        fy *= rd.sf;
-        fz *= rd.sf;
-    }
-    const int g = rd.base + ia;
-    if constexpr (MODE == kQuery) {
-        double* o = d.fq + 4 * (size_t)(rd.base + P::id(pi));
-        o[0] = (double)fx;
-        o[1] = (double)fy;
-        o[2] = (double)fz;
-        o[3] = (double)e;
-        return;
-    } else {
-        const real hh = MODE == kRefresh ? (real)0 : (real)sa.h;
-        typename P::vel_t v = P::vel(d)[g];
-        real vx = v.x + hh * fx, vy = v.y + hh * fy, vz = v.z + hh * fz;
-        if constexpr (MODE == kFused) {
-            const real c1 = (real)sa.c1;
-            const real c2 = (real)d.c2[r];
-            vx += hh * fx;
-            vy += hh * fy;
-            vz += hh * fz;
-            typename P::pos_t x = P::drift(pi, hh * vx, hh * vy, hh * vz, rd);
-            const uint4 w = draw(sa.seed, (uint32_t)P::id(pi), (uint32_t)step_next, (uint32_t)r, kPurposeOStep);
-            real z0, z1, z2;
-            if constexpr (P::kF64) {
-                normals3d(w, z0, z1, z2);
-            } else {
-                normals3f(w, z0, z1, z2);
-            }
-            vx = c1 * vx + c2 * z0;
-            vy = c1 * vy + c2 * z1;
-            vz = c1 * vz + c2 * z2;
-            x = P::drift(x, hh * vx, hh * vy, hh * vz, rd);
-            P::pos(d, cur ^ 1)[g] = x;
-            set_xyz<P>(v, vx, vy, vz);
-            P::vel(d)[g] = v;
-            real dx, dy, dz;
-            P::diff(x, P::xref(d)[g], rd, dx, dy, dz);
-            if (dx * dx + dy * dy + dz * dz > P::lim2(rd))
-                atomicOr(&d.flag[(size_t)(par ^ 1) * R + r], 1u);
-        } else {
-            set_xyz<P>(v, vx, vy, vz);
-            P::vel(d)[g] = v;
-            typename P::vel_t f;
-            f.x = fx;
-            f.y = fy;
-            f.z = fz;
-            f.w = 0;
-            P::frc(d)[g] = f;
-            if constexpr (MODE == kStopEnergy || MODE == kRefresh) P::epot(d)[g] = e;
-        }
-    }
+    force_atom<P, MODE, TPA>(d, sa, rd, r, ia, (int)(threadIdx.x % TPA), ia < rd.N, sa.cur, sa.step, sa.par);
 }
 
-// ---------------------------------------------------------------------------
-// Per-replica potential energy in FP64: fixed-order strided sums of the
-// per-atom energies, then a fixed tree; U = (1/2) sum_i e_i.
 template <class P>
 __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
 {
+    __shared__ double part[256];
     const int r = sa.r0 + blockIdx.x;
     const RepDev rd = d.rep[r];
-    __shared__ double part[256];
-    double s = 0.0;
-    const typename P::real* e = P::epot(d) + rd.base;
-    for (int i = threadIdx.x; i < rd.N; i += 256) s += (double)e[i];
-    part[threadIdx.x] = s;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) d.U[r] = 0.5 * part[0];
+    energy_replica<P>(d, rd, r, part);
 }
 
 // ---------------------------------------------------------------------------
@@ -582,8 +76,8 @@ __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
 // j = k mod 2 are paired; for the replicas a, b holding them
 // D = (1/T_j - 1/T_{j+1}) (U_a - U_b); the 53-bit uniform of the lower
 // replica id decides: accept iff D >= 0 or u < exp(D).  Accepted pairs swap
-// slots; every replica gets its velocity factor alpha = sqrt(T_new/T_old)
-// (1 if not swapped) and the noise amplitude of its new temperature.
+// slots; each swapped replica's pending velocity factor is multiplied by
+// sqrt(T_new/T_old) and it takes the noise amplitude of its new temperature.
 __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, int R, int64_t k, uint64_t seed,
                               double* alpha, double* c2, double c1sq, int64_t* att, int64_t* acc, XRec* log,
                               int64_t* log_count, int64_t log_cap, const int64_t* steps, int64_t step_all,
@@ -592,10 +86,7 @@ __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, 
     __shared__ int rep[4096];
     __shared__ int64_t lbase;
     const int tid = threadIdx.x, nt = blockDim.x;
-    for (int r = tid; r < R; r += nt) {
-        rep[slot[r]] = r;
-        if (alpha) alpha[r] = 1.0;
-    }
+    for (int r = tid; r < R; r += nt) rep[slot[r]] = r;
     if (tid == 0) lbase = log_count ? *log_count : 0;
     __syncthreads();
     const int j0 = (int)(k & 1);
@@ -631,9 +122,9 @@ __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, 
         if (ok) {
             slot[a] = j + 1;
             slot[b] = j;
-            if (alpha) {
-                alpha[a] = sqrt(Tb / Ta);
-                alpha[b] = sqrt(Ta / Tb);
+            if (alpha) {  // factors of consecutive exchanges compose
+                alpha[a] *= sqrt(Tb / Ta);
+                alpha[b] *= sqrt(Ta / Tb);
             }
             if (c2) {
                 c2[a] = sqrt((1.0 - c1sq) * Tb);

@@ -1,0 +1,481 @@
+// re_persist.hip -- the persistent engine: one launch advances every replica
+// for a whole re_step call.
+//
+// Each replica is served by a team of workgroups (team_size >= 1; teams of
+// one need no inter-workgroup synchronisation).  A team walks its replica
+// through BAOAB steps on its own schedule -- list updates, force phases and
+// exchange joins happen when that replica needs them -- so replicas
+// progress at their own speed and may have taken different numbers of steps
+// between exchange attempts (Implementation section: asynchronous
+// iteration).  Team members synchronise through a counter barrier with
+// agent-scope release/acquire; the leader (member 0) runs the reorder, the
+// energy sum and the exchange protocol.
+//
+// Exchange protocol, attempt k (k0 = first attempt of the call):
+//   gate     every replica has resolved attempt k-1 (the "done" counter
+//            reached R (k - k0)) -- the master's blocking gather of the
+//            temperatures in the paper;
+//   pattern  slots entering attempt k are in slotbuf[k & 1]; ladder pairs
+//            (j, j+1) with j = k mod 2;
+//   post     U and join step into the mailbox of parity k & 1, then the
+//            post counter (release);
+//   wait     for the partner's post (acquire) -- the paper's blocking
+//            receive of the (T, U, random) triplet;
+//   decide   both partners evaluate the same Metropolis rule with the
+//            Philox uniform of the lower replica id; the lower slot logs;
+//   resolve  new slot into slotbuf[(k+1) & 1], velocity factor, done += 1.
+// Triggers: synchronous mode joins at every multiple of N_x; asynchronous
+// mode lets master m_k = k mod R trigger attempt k after N_x of its own
+// steps since its previous attempt (the trigger counter), every other
+// replica joining at its next step boundary after it sees the trigger;
+// schedule mode joins at injected steps.  Every wait is bounded by the
+// watchdog; a timeout raises the abort flag and every team exits.
+#include "re_device.hpp"
+#include "re_persist.hpp"
+
+namespace re {
+
+__device__ __forceinline__ uint64_t clock100()
+{
+    return __builtin_amdgcn_s_memrealtime();  // 100 MHz constant clock
+}
+
+// Bounded waiting (thread 0 of a workgroup).  The watchdog counts time
+// without progress: any completed force phase anywhere (the heartbeat)
+// restarts it.  On expiry the abort flag is raised.
+struct Watch {
+    uint64_t t0, beat;
+};
+
+__device__ __forceinline__ Watch watch_start(const PersistArgs& pa)
+{
+    return Watch{clock100(), __hip_atomic_load(pa.st.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)};
+}
+
+// false: give up (abort raised or seen)
+__device__ __forceinline__ bool watch_tick(const PersistArgs& pa, Watch& w)
+{
+    if (__hip_atomic_load(pa.st.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+    const uint64_t b = __hip_atomic_load(pa.st.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t now = clock100();
+    if (b != w.beat) {
+        w.beat = b;
+        w.t0 = now;
+    } else if (now - w.t0 > pa.timeout) {
+        atomicOr(pa.st.abort, 1u);
+        atomicOr(pa.st.err, kErrTimeout);
+        return false;
+    }
+    return true;
+}
+
+// thread 0 of a workgroup: spin until *p >= v (agent scope)
+__device__ bool wait_ge_u64(const PersistArgs& pa, const uint64_t* p, uint64_t v)
+{
+    Watch w = watch_start(pa);
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < v) {
+        __builtin_amdgcn_s_sleep(2);
+        if (!watch_tick(pa, w)) return false;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+__device__ bool wait_ge_i64(const PersistArgs& pa, const int64_t* p, int64_t v)
+{
+    return wait_ge_u64(pa, reinterpret_cast<const uint64_t*>(p), (uint64_t)v);
+}
+
+// Team barrier: a counter per team with agent-scope release/acquire (the
+// workgroups of a team may sit on different XCDs, whose L2s are not
+// coherent without the write-back/invalidate these fences imply).
+// Returns false when the run is being aborted.
+__device__ bool team_sync(const PersistArgs& pa, unsigned* ctr, unsigned& epoch, int t, int* s_ok)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (t > 1) {
+            ++epoch;
+            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const unsigned tgt = epoch * (unsigned)t;
+            Watch w = watch_start(pa);
+            while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tgt) {
+                __builtin_amdgcn_s_sleep(1);
+                if (!watch_tick(pa, w)) {
+                    ok = 0;
+                    break;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        } else if (__hip_atomic_load(pa.st.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+            ok = 0;
+        }
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+// The exchange join of replica r at its boundary s (energy U) for attempt k,
+// run by the whole leader workgroup.  Returns false on abort.
+__device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const CallParams& cp, int r, int64_t k,
+                              int64_t s, double U, int* sh)
+{
+    const PersistState& ps = pa.st;
+    const int R = pa.sa.R;
+    const int p = (int)(k & 1);
+    if (threadIdx.x == 0) {
+        int ok = wait_ge_u64(pa, ps.xdone, (uint64_t)R * (uint64_t)(k - cp.k0)) ? 1 : 0;
+        if (ok && cp.mode == kModeAsync && (int)(k % R) == r) {
+            // the master publishes the trigger of attempt k
+            __hip_atomic_fetch_max(ps.trig, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sh[0] = ok;
+        sh[1] = -1;
+    }
+    __syncthreads();
+    if (!sh[0]) return false;
+    const int32_t* sb = ps.slotbuf + (size_t)p * R;
+    const int jme = sb[r];
+    const int off = jme - p;
+    int jp = -1;
+    if (off >= 0 && (off & 1) == 0 && jme + 1 < R) jp = jme + 1;
+    if (off >= 0 && (off & 1) == 1) jp = jme - 1;
+    if (jp >= 0)
+        for (int q = threadIdx.x; q < R; q += blockDim.x)
+            if (sb[q] == jp) sh[1] = q;
+    __syncthreads();
+    int ok = 1;
+    if (threadIdx.x == 0) {
+        const int q = sh[1];
+        ps.upost[(size_t)p * R + r] = U;
+        ps.spost[(size_t)p * R + r] = s;
+        __hip_atomic_store(ps.post + r, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        int newslot = jme;
+        if (q >= 0) {
+            ok = wait_ge_i64(pa, ps.post + q, k + 1) ? 1 : 0;
+            if (ok) {
+                const double Uq = ps.upost[(size_t)p * R + q];
+                const int64_t sq = ps.spost[(size_t)p * R + q];
+                const int jlo = jme < jp ? jme : jp;
+                const int a = jme < jp ? r : q, b = jme < jp ? q : r;
+                const double Ua = jme < jp ? U : Uq, Ub = jme < jp ? Uq : U;
+                const double Ta = d.Tl[jlo], Tb = d.Tl[jlo + 1];
+                const double delta = (1.0 / Ta - 1.0 / Tb) * (Ua - Ub);
+                const double u = uniform53(pa.sa.seed, k, a < b ? a : b);
+                const int acc = (delta >= 0.0 || u < exp(delta)) ? 1 : 0;
+                if (jme == jlo) {
+                    atomicAdd((unsigned long long*)&d.attempts[jlo], 1ull);
+                    if (acc) atomicAdd((unsigned long long*)&d.accepts[jlo], 1ull);
+                    const int64_t li = (int64_t)atomicAdd((unsigned long long*)d.log_count, 1ull);
+                    XRec rec;
+                    rec.attempt = k;
+                    rec.master = cp.mode == kModeAsync ? (int32_t)(k % R) : -1;
+                    rec.slot_lo = jlo;
+                    rec.rep_a = a;
+                    rec.rep_b = b;
+                    rec.step_a = jme < jp ? s : sq;
+                    rec.step_b = jme < jp ? sq : s;
+                    rec.U_a = Ua;
+                    rec.U_b = Ub;
+                    rec.T_a = Ta;
+                    rec.T_b = Tb;
+                    rec.u = u;
+                    rec.accepted = acc;
+                    rec.pad_ = 0;
+                    d.log[li % pa.log_cap] = rec;
+                }
+                if (acc) {
+                    newslot = jp;
+                    d.alpha[r] *= sqrt(d.Tl[jp] / d.Tl[jme]);
+                    d.c2[r] = sqrt((1.0 - pa.c1sq) * d.Tl[jp]);
+                    ps.apend[r] = 1;
+                }
+            }
+        }
+        if (ok) {
+            ps.slotbuf[(size_t)(p ^ 1) * R + r] = newslot;
+            d.slot[r] = newslot;
+            __hip_atomic_fetch_add(ps.xdone, 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        sh[0] = ok;
+    }
+    __syncthreads();
+    return sh[0] != 0;
+}
+
+// control word of a boundary: bit 0 stop at the next force phase, bit 1 join
+// at that boundary, bit 2 leave the run here
+constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4;
+
+template <class P, int TPA>
+__global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
+{
+    __shared__ int cnt[kMaxCells + 1];
+    __shared__ int part[1024];
+    __shared__ double dpart[1024];
+    __shared__ int sh[4];
+    const PersistState& ps = pa.st;
+    const CallParams& cp = *pa.call;
+    const int b = blockIdx.x;
+    const int r = pa.team_rep[b];
+    if (r < 0) return;
+    const int m = pa.team_mem[b], t = pa.team_size[b];
+    unsigned* ctr = pa.bar + 64 * (size_t)pa.team_id[b];
+    const bool leader = m == 0;
+    const RepDev rd = d.rep[r];
+    const int R = pa.sa.R;
+    const int chunk = (rd.N + t - 1) / t;
+    const int i0 = min(rd.N, m * chunk), i1 = min(rd.N, i0 + chunk);
+    const int tid = threadIdx.x, nt = blockDim.x;
+    unsigned epoch = 0;
+    // per-replica state, identical in every member
+    int64_t s = d.steps[r];
+    const int cur0 = cp.cur0;
+    int cur = cur0;
+    int64_t knext = ps.katt[r];
+    int64_t jprev = ps.jprev[r];
+    int64_t asched = 0;  // next scheduled attempt (schedule mode)
+    int64_t target = cp.mode == kModeSchedule ? 0 : cp.target[r];
+    bool join_pending = false;
+    bool parked = false;
+    double Ucur = d.U[r];
+
+    // plan for the force phase that ends at boundary sn (leader only)
+    auto plan = [&](int64_t sn) -> int {
+        int c = 0;
+        if (cp.mode == kModeSync) {
+            if (sn % pa.Nx == 0) c |= kCtlStop | kCtlJoin;
+            if (sn >= target) c |= kCtlStop;
+        } else if (cp.mode == kModeSchedule) {
+            if (asched < cp.A && sn == cp.sched[asched * R + r]) c |= kCtlStop | kCtlJoin;
+        } else {
+            const bool master = (int)(knext % R) == r;
+            if (master && sn == jprev + pa.Nx) c |= kCtlStop | kCtlJoin;
+            if (!master &&
+                __hip_atomic_load(ps.trig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint64_t)knext)
+                c |= kCtlStop | kCtlJoin;
+            if (sn >= target) c |= kCtlStop;
+        }
+        return c;
+    };
+
+    bool ok = true;
+    int ctl = 0;
+    while (ok) {
+        // ---- at a stopped boundary s
+        if (leader) {
+            if (join_pending) {
+                ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
+                knext += 1;
+                jprev = s;
+                if (cp.mode == kModeSchedule) asched += 1;
+                join_pending = false;
+            }
+            int c = 0;
+            if (ok) {
+                bool done;
+                if (cp.mode == kModeSync)
+                    done = s >= target;
+                else if (cp.mode == kModeSchedule)
+                    done = asched >= cp.A;
+                else
+                    done = s >= target;
+                if (done && cp.mode == kModeAsync) {
+                    // parked: take part in attempts triggered by others until
+                    // every replica is parked and no attempt is in flight
+                    if (!parked && tid == 0) __hip_atomic_fetch_add(ps.parked, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                    parked = true;
+                    Watch w{};
+                    if (tid == 0) w = watch_start(pa);
+                    while (ok) {
+                        if (tid == 0) {
+                            const uint64_t tr = __hip_atomic_load(ps.trig, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint64_t pk = __hip_atomic_load(ps.parked, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            const uint64_t xd = __hip_atomic_load(ps.xdone, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+                            int act = 0;
+                            if (tr > (uint64_t)knext)
+                                act = 1;  // join
+                            else if (pk == (uint64_t)R && xd == (uint64_t)R * (tr - (uint64_t)cp.k0))
+                                act = 2;  // everyone parked, nothing in flight
+                            else if (!watch_tick(pa, w))
+                                act = 3;
+                            else
+                                __builtin_amdgcn_s_sleep(4);
+                            sh[2] = act;
+                        }
+                        __syncthreads();
+                        const int act = sh[2];
+                        __syncthreads();
+                        if (act == 1) {
+                            ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
+                            knext += 1;
+                            jprev = s;
+                        } else if (act == 2) {
+                            break;
+                        } else if (act == 3) {
+                            ok = false;
+                        }
+                    }
+                    c = kCtlExit;
+                } else if (done) {
+                    c = kCtlExit;
+                } else {
+                    c = plan(s + 1);
+                }
+            }
+            if (!ok) c = kCtlExit;
+            if (tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = c;
+        }
+        if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+            ok = false;
+            break;
+        }
+        ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ctl & kCtlExit) break;
+        // ---- first half of step s -> s+1
+        {
+            const bool apply = __hip_atomic_load(ps.apend + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            for (int i = i0 + tid; i < i1; i += nt) start_atom<P>(d, pa.sa, rd, r, i, cur, s, apply);
+        }
+        if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+            ok = false;
+            break;
+        }
+        if (leader && tid == 0) {
+            d.alpha[r] = 1.0;
+            ps.apend[r] = 0;
+        }
+        // ---- steps that end at a fused boundary loop here
+        for (;;) {
+            const int par = (int)((s + 1) & 1);
+            const bool rebuild =
+                __hip_atomic_load(d.flag + (size_t)par * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            if (rebuild) {
+                if (leader) reorder_replica<P>(d, rd, r, cur, cnt, part);
+                if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+                    ok = false;
+                    break;
+                }
+                const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
+                for (int base = i0; base < i1; base += nt / 32) {
+                    const int i = base + tid / 32;
+                    list_rows<P>(d, rd, pos, i, i < i1, tid & 31, pa.sa.tpa, pa.sa.M);
+                }
+                if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+                    ok = false;
+                    break;
+                }
+            }
+            const bool stop = (ctl & kCtlStop) != 0;
+            const int apb = nt / TPA;
+            for (int base = i0; base < i1; base += apb) {
+                const int ia = base + tid / TPA;
+                if (stop)
+                    force_atom<P, kStopEnergy, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+                else
+                    force_atom<P, kFused, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+            }
+            if (leader && !stop && tid == 0) ps.ctl[(size_t)((s + 2) & 1) * R + r] = plan(s + 2);
+            if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+                ok = false;
+                break;
+            }
+            if (leader && tid == 0) {
+                d.flag[(size_t)par * R + r] = 0u;
+                __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            s += 1;
+            if (stop) {
+                if (leader) {
+                    energy_replica<P>(d, rd, r, dpart);
+                    Ucur = d.U[r];
+                }
+                join_pending = (ctl & kCtlJoin) != 0;
+                break;
+            }
+            cur ^= 1;
+            ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+    // ---- leave at a stopped boundary: positions back into the call's buffer
+    if (cur != cur0) {
+        typename P::pos_t* src = P::pos(d, cur) + rd.base;
+        typename P::pos_t* dst = P::pos(d, cur0) + rd.base;
+        for (int i = i0 + tid; i < i1; i += nt) dst[i] = src[i];
+    }
+    if (leader && tid == 0) {
+        d.steps[r] = s;
+        ps.katt[r] = knext;
+        ps.jprev[r] = jprev;
+    }
+}
+
+// Reset of the per-call counters and the slots entering the first attempt.
+__global__ void k_persist_prepare(DevState d, PersistArgs pa, int nteams)
+{
+    const PersistState& ps = pa.st;
+    const CallParams& cp = *pa.call;
+    const int R = pa.sa.R;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R) {
+        ps.slotbuf[(size_t)(cp.k0 & 1) * R + i] = d.slot[i];
+        ps.katt[i] = cp.k0;
+    }
+    if (i < 64 * nteams) pa.bar[i] = 0u;
+    if (i == 0) {
+        *ps.xdone = 0ull;
+        *ps.trig = (uint64_t)cp.k0;
+        *ps.parked = 0u;
+        *ps.abort = 0u;
+        *ps.err = 0u;
+        *ps.beat = 0ull;
+    }
+}
+
+template <class P>
+static hipError_t persist_t(const DevState& d, const PersistArgs& pa, int nblk, hipStream_t st)
+{
+    switch (pa.sa.tpa) {
+    case 1: hipLaunchKernelGGL((k_persist<P, 1>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 2: hipLaunchKernelGGL((k_persist<P, 2>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 4: hipLaunchKernelGGL((k_persist<P, 4>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 8: hipLaunchKernelGGL((k_persist<P, 8>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, int nblk, int nteams, hipStream_t st)
+{
+    const int n = std::max(pa.sa.R, 64 * nteams);
+    hipLaunchKernelGGL(k_persist_prepare, dim3((n + 255) / 256), dim3(256), 0, st, d, pa, nteams);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return fp64 ? persist_t<PF64>(d, pa, nblk, st) : persist_t<PMixed>(d, pa, nblk, st);
+}
+
+hipError_t persist_occupancy(bool fp64, int tpa, int* blocks_per_cu)
+{
+    const void* f = nullptr;
+    if (fp64) {
+        switch (tpa) {
+        case 1: f = (const void*)k_persist<PF64, 1>; break;
+        case 2: f = (const void*)k_persist<PF64, 2>; break;
+        case 4: f = (const void*)k_persist<PF64, 4>; break;
+        default: f = (const void*)k_persist<PF64, 8>; break;
+        }
+    } else {
+        switch (tpa) {
+        case 1: f = (const void*)k_persist<PMixed, 1>; break;
+        case 2: f = (const void*)k_persist<PMixed, 2>; break;
+        case 4: f = (const void*)k_persist<PMixed, 4>; break;
+        default: f = (const void*)k_persist<PMixed, 8>; break;
+        }
+    }
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 1024, 0);
+}
+
+}  // namespace re
