@@ -351,13 +351,25 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
     const int n0 = e0 - s0, len = n0 + (e1 - s1);
     uint64_t mask = 0;
     int cnt = 0;
-    for (int k = 0; k < len; ++k) {
-        const int j = k < n0 ? s0 + k : s1 + (k - n0);
-        real dx, dy, dz;
-        P::diff(pi, pos[j], rd, dx, dy, dz);
-        if (dx * dx + dy * dy + dz * dz < rl2 && j != i) {
-            if (k < 64) mask |= 1ull << k;
-            ++cnt;
+    // four candidates in flight per lane
+    for (int k0 = 0; k0 < len; k0 += 4) {
+        typename P::pos_t pj[4];
+        int jj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;
+            jj[u] = k < len ? (k < n0 ? s0 + k : s1 + (k - n0)) : i;
+            pj[u] = pos[jj[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + u;
+            real dx, dy, dz;
+            P::diff(pi, pj[u], rd, dx, dy, dz);
+            if (k < len && dx * dx + dy * dy + dz * dz < rl2 && jj[u] != i) {
+                if (k < 64) mask |= 1ull << k;
+                ++cnt;
+            }
         }
     }
     int off = cnt;
@@ -440,9 +452,8 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
             const float rc2 = rd.rc2f, lo = rd.near_lo, hi = rd.near_hi, is2 = rd.inv_s2f;
             const float ushift = (float)sa.ushiftd;
             const uint64_t thr = rd.rc2_exact;
-            for (int kk = 0; kk < nrow; ++kk) {
-                const uint32_t j = nlp[(size_t)kk * stride];
-                const int4 pj = pos[j];
+            // one pair: pj is the neighbour, ok false for padding entries
+            auto pair = [&](const int4& pj, bool ok) {
                 const int ix = PMixed::wrapdiff(pi.x, pj.x);
                 const int iy = PMixed::wrapdiff(pi.y, pj.y);
                 const int iz = PMixed::wrapdiff(pi.z, pj.z);
@@ -455,6 +466,7 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
                                         (uint64_t)((int64_t)iz * iz);
                     in = e2 < thr;
                 }
+                in = in && ok;
                 const float ir2 = __builtin_amdgcn_rcpf(r2) * is2;
                 const float ir6 = ir2 * ir2 * ir2;
                 const float ff = in ? ir2 * ir6 * __builtin_fmaf(48.0f, ir6, -24.0f) : 0.0f;
@@ -462,6 +474,30 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
                 fy = __builtin_fmaf(ff, dy, fy);
                 fz = __builtin_fmaf(ff, dz, fz);
                 if constexpr (kEnergy) e += in ? __builtin_fmaf(4.0f * ir6, ir6, -4.0f * ir6) - ushift : 0.0f;
+            };
+            // four neighbours in flight: the indices of the next four are
+            // loaded while the current four are computed
+            constexpr int U = 4;
+            // (rows past the atom's own entries are read unconditionally -- the
+            // list allocation has kListSlackRows rows of slack -- and replaced
+            // by the atom itself, which the ok flag then masks)
+            uint32_t jn[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint32_t ld = nlp[(size_t)u * stride];
+                jn[u] = u < nrow ? ld : (uint32_t)ia;
+            }
+            for (int kk = 0; kk < nrow; kk += U) {
+                int4 pj[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) pj[u] = pos[jn[u]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t ld = nlp[(size_t)(kk + U + u) * stride];
+                    jn[u] = kk + U + u < nrow ? ld : (uint32_t)ia;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) pair(pj[u], kk + u < nrow);
             }
         }
     }

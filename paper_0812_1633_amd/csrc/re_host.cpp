@@ -807,7 +807,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.cellid, slots);
     ALLOC(d.rank, slots);
     ALLOC(d.cell_start, cells);
-    ALLOC(d.nl, nl);
+    ALLOC(d.nl, nl + (int64_t)kListSlackRows * 8 * ((c->nmax + 63) / 64 * 64));
     ALLOC(d.nn, slots);
     ALLOC(d.rep, R);
     ALLOC(d.slot, R);
