@@ -306,50 +306,71 @@ __device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int 
 // radius, cells ordered z fastest): the candidates of an atom are the atoms
 // of the 5 x 5 x 5 cells around its own, i.e. 25 rows of 5 consecutive
 // cells, each row one or two contiguous slot ranges of the cell-sorted
-// arrays (all cells when there are fewer than 5 per side).  A group of 32
-// lanes serves one atom, lane q scanning row q: it counts its hits and keeps
-// them as a bit mask, a shuffle scan over the group gives each lane its
-// first list entry, then the lane writes its hits.
+// arrays (all cells when there are fewer than 5 per side).  A group of LPA
+// lanes serves one atom, lane q scanning rows q, q + LPA, ...: it counts its
+// hits and keeps them as a bit mask, a shuffle scan over the group gives
+// each lane its first list entry, then the lane writes its hits.
 // Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa].
-template <class P>
+template <class P, int LPA>
 __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int i,
                                           bool act, int q, int tpa, int M)
 {
     using real = typename P::real;
+    constexpr int RPL = (25 + LPA - 1) / LPA;  // rows per lane
     const int nc = rd.ncell;
     const int32_t* cs = d.cell_start + rd.cell_base;
     const typename P::pos_t pi = pos[act ? i : 0];
-    int s0 = 0, e0 = 0, s1 = 0, e1 = 0;
+    // this lane's candidates: up to 2 RPL contiguous slot ranges
+    int sr[2 * RPL], er[2 * RPL];
+#pragma unroll
+    for (int k = 0; k < 2 * RPL; ++k) sr[k] = er[k] = 0;
     if (act) {
         const int cx = P::cellc(pi.x, rd), cy = P::cellc(pi.y, rd), cz = P::cellc(pi.z, rd);
-        if (nc >= 5) {
-            if (q < 25) {
-                const int x = (cx + q / 5 - 2 + nc) % nc, y = (cy + q % 5 - 2 + nc) % nc;
-                const int rb = (x * nc + y) * nc;
-                const int z0 = cz - 2, z1 = cz + 2;
-                if (z0 < 0) {
-                    s0 = cs[rb + z0 + nc];
-                    e0 = cs[rb + nc];
-                    s1 = cs[rb];
-                    e1 = cs[rb + z1 + 1];
-                } else if (z1 >= nc) {
-                    s0 = cs[rb + z0];
-                    e0 = cs[rb + nc];
-                    s1 = cs[rb];
-                    e1 = cs[rb + z1 - nc + 1];
-                } else {
-                    s0 = cs[rb + z0];
-                    e0 = cs[rb + z1 + 1];
+#pragma unroll
+        for (int w = 0; w < RPL; ++w) {
+            const int row = q + w * LPA;
+            if (nc >= 5) {
+                if (row < 25) {
+                    const int x = (cx + row / 5 - 2 + nc) % nc, y = (cy + row % 5 - 2 + nc) % nc;
+                    const int rb = (x * nc + y) * nc;
+                    const int z0 = cz - 2, z1 = cz + 2;
+                    if (z0 < 0) {
+                        sr[2 * w] = cs[rb + z0 + nc];
+                        er[2 * w] = cs[rb + nc];
+                        sr[2 * w + 1] = cs[rb];
+                        er[2 * w + 1] = cs[rb + z1 + 1];
+                    } else if (z1 >= nc) {
+                        sr[2 * w] = cs[rb + z0];
+                        er[2 * w] = cs[rb + nc];
+                        sr[2 * w + 1] = cs[rb];
+                        er[2 * w + 1] = cs[rb + z1 - nc + 1];
+                    } else {
+                        sr[2 * w] = cs[rb + z0];
+                        er[2 * w] = cs[rb + z1 + 1];
+                    }
                 }
+            } else if (row < nc * nc) {
+                sr[2 * w] = cs[row * nc];
+                er[2 * w] = cs[row * nc + nc];
             }
-        } else if (q < nc * nc) {
-            s0 = cs[q * nc];
-            e0 = cs[q * nc + nc];
         }
     }
+    int len = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * RPL; ++k) len += er[k] - sr[k];
+    // candidate number k -> slot
+    auto slot_of = [&](int k) {
+        int j = i;
+#pragma unroll
+        for (int r = 0; r < 2 * RPL; ++r) {
+            const int n = er[r] - sr[r];
+            if (k >= 0 && k < n) j = sr[r] + k;
+            k -= n;
+        }
+        return j;
+    };
     const real rl2 = P::rl2(rd);
-    const int n0 = e0 - s0, len = n0 + (e1 - s1);
-    uint64_t mask = 0;
+    uint64_t mask0 = 0, mask1 = 0;
     int cnt = 0;
     // four candidates in flight per lane
     for (int k0 = 0; k0 < len; k0 += 4) {
@@ -357,8 +378,7 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         int jj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u;
-            jj[u] = k < len ? (k < n0 ? s0 + k : s1 + (k - n0)) : i;
+            jj[u] = k0 + u < len ? slot_of(k0 + u) : i;
             pj[u] = pos[jj[u]];
         }
 #pragma unroll
@@ -367,17 +387,20 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
             real dx, dy, dz;
             P::diff(pi, pj[u], rd, dx, dy, dz);
             if (k < len && dx * dx + dy * dy + dz * dz < rl2 && jj[u] != i) {
-                if (k < 64) mask |= 1ull << k;
+                if (k < 64)
+                    mask0 |= 1ull << k;
+                else if (k < 128)
+                    mask1 |= 1ull << (k - 64);
                 ++cnt;
             }
         }
     }
     int off = cnt;
-    for (int m = 1; m < 32; m <<= 1) {
-        const int v = __shfl_up(off, m, 32);
+    for (int m = 1; m < LPA; m <<= 1) {
+        const int v = __shfl_up(off, m, LPA);
         if (q >= m) off += v;
     }
-    const int tot = __shfl(off, 31, 32);
+    const int tot = __shfl(off, LPA - 1, LPA);
     off -= cnt;
     uint32_t* nl = d.nl + rd.nl_base;
     const size_t Np = (size_t)rd.Np;
@@ -385,15 +408,20 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         if (off < M) nl[((size_t)(off / tpa) * Np + i) * tpa + (off % tpa)] = (uint32_t)j;
         ++off;
     };
-    if (len <= 64) {
-        while (mask) {
-            const int k = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            put(k < n0 ? s0 + k : s1 + (k - n0));
+    if (len <= 128) {
+        while (mask0) {
+            const int k = __builtin_ctzll(mask0);
+            mask0 &= mask0 - 1;
+            put(slot_of(k));
+        }
+        while (mask1) {
+            const int k = __builtin_ctzll(mask1);
+            mask1 &= mask1 - 1;
+            put(slot_of(k + 64));
         }
     } else {
         for (int k = 0; k < len; ++k) {
-            const int j = k < n0 ? s0 + k : s1 + (k - n0);
+            const int j = slot_of(k);
             real dx, dy, dz;
             P::diff(pi, pos[j], rd, dx, dy, dz);
             if (dx * dx + dy * dy + dz * dz < rl2 && j != i) put(j);

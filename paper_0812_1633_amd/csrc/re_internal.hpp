@@ -10,6 +10,7 @@ namespace re {
 constexpr int kMaxCellsPerSide = 32;               // cell grid cap (cells may exceed r_list/2)
 constexpr int kMaxCells = kMaxCellsPerSide * kMaxCellsPerSide * kMaxCellsPerSide;
 constexpr int kReorderThreads = 1024;              // one workgroup per replica
+constexpr int kListLanes = 8;                      // list-build lanes per atom (fixes the list order)
 constexpr int kListSlackRows = 8;                  // list rows read past a replica's block by the
                                                    // force loop's prefetch (values unused)
 constexpr uint32_t kPurposeInitVel = 0u;           // Philox counter word 3 ("purpose")

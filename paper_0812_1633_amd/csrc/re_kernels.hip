@@ -31,17 +31,18 @@ __global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArg
     reorder_replica<P>(d, rd, r, sa.cur, cnt, part);
 }
 
-// blockIdx.y = replica (from r0), 8 atoms (32 lanes each) per block.
+// blockIdx.y = replica (from r0), 256 / kListLanes atoms per block.
 template <class P>
 __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
 {
+    constexpr int APB = 256 / kListLanes;  // atoms per block
     const int r = sa.r0 + blockIdx.y;
     if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
     const RepDev rd = d.rep[r];
-    const int i = blockIdx.x * 8 + (threadIdx.x >> 5);
-    if (blockIdx.x * 8 >= rd.N) return;
+    const int i = blockIdx.x * APB + (int)(threadIdx.x / kListLanes);
+    if ((int)blockIdx.x * APB >= rd.N) return;
     const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
-    list_rows<P>(d, rd, pos, i, i < rd.N, threadIdx.x & 31, sa.tpa, sa.M);
+    list_rows<P, kListLanes>(d, rd, pos, i, i < rd.N, (int)(threadIdx.x % kListLanes), sa.tpa, sa.M);
 }
 
 // Force + epilogue; the first block of each replica also marks the list of
@@ -223,7 +224,8 @@ hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int 
 hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int nmax, hipStream_t st)
 {
     if (nrep <= 0) return hipSuccess;
-    const dim3 grid((nmax + 7) / 8, nrep);
+    const int apb = 256 / kListLanes;
+    const dim3 grid((nmax + apb - 1) / apb, nrep);
     if (fp64)
         hipLaunchKernelGGL(k_listrows<PF64>, grid, dim3(256), 0, st, d, sa);
     else

@@ -359,9 +359,9 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     break;
                 }
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-                for (int base = i0; base < i1; base += nt / 32) {
-                    const int i = base + tid / 32;
-                    list_rows<P>(d, rd, pos, i, i < i1, tid & 31, pa.sa.tpa, pa.sa.M);
+                for (int base = i0; base < i1; base += nt / kListLanes) {
+                    const int i = base + tid / kListLanes;
+                    list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M);
                 }
                 if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
                     ok = false;
