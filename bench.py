@@ -49,7 +49,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="lj-32x4000")
-    ap.add_argument("--engine", default=None, help="persistent | lockstep (default: the library default)")
+    ap.add_argument("--engine", default=None, help="persistent | lockstep (default: autotuned)")
     ap.add_argument("--plain-steps", type=int, default=100)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -69,11 +69,17 @@ def main():
     rc, skin, dt, Nx, seed = cfg["rc"], cfg["skin"], cfg["dt"], cfg["Nx"], cfg["seed"]
     atoms = int(N.sum())
     kw = dict(rho_per_replica=rho, gamma=cfg["gamma"])
+    tune = {}
     if args.engine:
-        kw["engine"] = args.engine
+        tune["engine"] = args.engine
+    else:
+        tune["autotune"] = True
+        tune["tune_cache"] = os.path.join(ROOT, "gpurun_out", "tune_cache.json")
+        os.makedirs(os.path.dirname(tune["tune_cache"]), exist_ok=True)
 
     # ---- batched mixed-precision form ------------------------------------
-    eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw)
+    eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune)
+    engine_used, tpa_used, team_used = eng.query_config()
     eng.step(args.warmup)
     steps0, reb0 = eng.query_steps()
     torch.cuda.synchronize()
@@ -114,14 +120,17 @@ def main():
     tol["energy_rel_max"] = abs(Ug - Uo) / abs(Uo)
     ok = tol["force_normwise_max"] <= 1e-5 and tol["energy_rel_max"] <= 1e-5
 
-    # algorithmic flops of one fused force launch: 27 per unique in-cutoff
-    # pair and 9 per unique pair in the skin shell, per replica, scaled by N
+    # algorithmic flops per atom-step: 27 per unique in-cutoff pair and 9 per
+    # unique pair in the skin shell (measured pair counts of two replicas).
+    # The lockstep engine's dominant kernel does one step of every replica
+    # per launch; the persistent kernel does the whole timed run.
     flop_per_atom = np.mean([(27 * c + 9 * s) / n for c, s, n in counts])
-    flops_launch = flop_per_atom * atoms
+    flops_launch = flop_per_atom * (atoms if engine_used == "lockstep" else done / max(1, k_n))
     achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
-                "kernel": "k_force<PMixed,fused>", "kernel_ms": k_ms, "launches_timed": k_n,
+                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed>",
+                "kernel_ms": k_ms, "launches_timed": k_n,
                 "flop_per_atom_step": float(flop_per_atom)}
     eng.close()
 
@@ -164,7 +173,9 @@ def main():
                       "rho": float(rho[0]) if len(set(rho.tolist())) == 1 else "uneven",
                       "T_ladder": [float(T[0]), float(T[-1])], "r_c": rc, "skin": skin, "dt": dt, "N_x": Nx,
                       "precision": "FP32 pair arithmetic, 32-bit fixed-point positions, FP64 energies/exchange",
-                      "engine": args.engine or "default", "parallelism": "replicas batched on 1 GPU"},
+                      "engine": engine_used, "threads_per_atom": tpa_used, "team_size": team_used,
+                      "tuning": "explicit" if args.engine else "autotuned",
+                      "parallelism": "replicas batched on 1 GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain,
            "tolerance": dict(tol, passed=bool(ok)),
            "exchange": {"attempts": int(acc_att.sum()), "accepted": int(acc_acc.sum())},

@@ -77,6 +77,12 @@ typedef struct {
     int block_size;              /* threads per block of the wide kernels; 0: auto */
     int team_size;               /* persistent engine: workgroups per replica; 0: auto */
     const char* tune_cache;      /* autotuner JSON cache path; NULL: no cache file */
+    int autotune;                /* nonzero: choose the batched engine and
+                                    threads_per_atom by timing short runs of each
+                                    candidate on throwaway contexts of the same
+                                    workload (or take the choice from tune_cache);
+                                    explicit engine/threads_per_atom settings are
+                                    then ignored */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */
@@ -203,6 +209,12 @@ int re_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int n, double*
  * window and their mean duration in milliseconds. */
 int re_profile(re_ctx* ctx, int enable);
 int re_query_kernel_time(re_ctx* ctx, double* mean_ms, int64_t* n);
+
+/* The launch configuration the context runs with (after autotuning):
+ * engine (RE_LOCKSTEP | RE_PERSISTENT; RE_PLAIN form: RE_LOCKSTEP),
+ * threads_per_atom, and the persistent team size of replica 0 (0 when the
+ * persistent engine is not available). */
+int re_query_config(re_ctx* ctx, int* engine, int* threads_per_atom, int* team_size);
 
 /* Free everything owned by the context (NULL is allowed). */
 void re_destroy(re_ctx* ctx);

@@ -6,6 +6,7 @@
 // entry point of include/re.h.
 #include "re_internal.hpp"
 #include "re_persist.hpp"
+#include "re_tune.hpp"
 #include "../../include/re.h"
 
 #include <algorithm>
@@ -668,6 +669,20 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         return fail(nullptr, RE_EINVAL, "block_size must be 64, 128 or 256");
     const double gamma = o.gamma_set ? o.gamma : 1.0;
     if (!(gamma >= 0)) return fail(nullptr, RE_EINVAL, "gamma must be >= 0");
+    if (o.autotune && o.form == RE_BATCHED) {
+        // the engine and lanes per atom of this size class: cached, or timed
+        const std::string key =
+            tune_key(R, N_atoms, o.rho_per_replica, rho, r_c, skin, o.precision, o.exchange_mode);
+        TuneChoice ch{};
+        if (!tune_lookup(o.tune_cache, key, ch)) {
+            const int rt = tune_run(R, N_atoms, T_ladder, rho, r_c, skin, dt, N_x, seed, o, ch);
+            if (rt != RE_OK) return fail(nullptr, rt, "autotuning failed: %s", g_noctx_error.c_str());
+            tune_store(o.tune_cache, key, ch);
+        }
+        o.batched_engine = ch.engine;
+        o.threads_per_atom = ch.tpa;
+        o.autotune = 0;
+    }
     if (o.form == RE_PLAIN && o.exchange_mode == RE_ASYNC)
         return fail(nullptr, RE_EINVAL, "the plain per-replica form runs synchronous exchanges only");
     const double rlist = r_c + skin;
@@ -1076,6 +1091,16 @@ int re_compute_forces(re_ctx* c, int r, double* F, double* U)
         u += q[4 * i + 3];
     }
     if (U) *U = 0.5 * u;
+    return RE_OK;
+}
+
+int re_query_config(re_ctx* c, int* engine, int* threads_per_atom, int* team_size)
+{
+    if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
+    const bool pers = c->form == RE_BATCHED && (c->engine == RE_PERSISTENT || c->xmode == RE_ASYNC);
+    if (engine) *engine = pers ? RE_PERSISTENT : RE_LOCKSTEP;
+    if (threads_per_atom) *threads_per_atom = c->cfg.tpa;
+    if (team_size) *team_size = c->pers_ok && !c->team_of.empty() ? c->team_of[0] : 0;
     return RE_OK;
 }
 

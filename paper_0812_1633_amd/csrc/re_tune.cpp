@@ -1,0 +1,178 @@
+// re_tune.cpp -- the autotuner: per workload size class, the batched engine
+// (lockstep or persistent) and the force kernel's lanes per atom are chosen
+// by timing short runs of every candidate on throwaway contexts of the same
+// workload.  Choices are kept in-process and, when a cache path is given, in
+// a small JSON file keyed by the size class.
+#include "re_tune.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <string>
+#include <vector>
+
+namespace re {
+
+static std::mutex g_mu;
+static std::map<std::string, TuneChoice> g_mem;
+
+// Size class: device, precision, exchange mode, replica count, the median
+// and the spread of the atom counts (log2 bins), the mean density (0.05
+// bins), r_c and the list radius.
+std::string tune_key(int R, const int32_t* N, const double* rho_r, double rho, double rc, double skin, int prec,
+                     int xmode)
+{
+    std::vector<int32_t> n(N, N + R);
+    std::sort(n.begin(), n.end());
+    const int med = n[R / 2];
+    double rs = 0;
+    for (int r = 0; r < R; ++r) rs += rho_r ? rho_r[r] : rho;
+    rs /= R;
+    char arch[64] = "gpu";
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::snprintf(arch, sizeof arch, "%s", prop.gcnArchName);
+        for (char* p = arch; *p; ++p)
+            if (*p == ':') *p = '+';
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s|p%d|x%d|R%d|N%d|S%d|rho%.2f|rc%.3f|rl%.3f", arch, prec, xmode, R,
+                  (int)std::lround(std::log2((double)med) * 2.0),
+                  (int)std::lround(std::log2((double)n[R - 1] / (double)n[0])), std::round(rs * 20.0) / 20.0, rc,
+                  rc + skin);
+    return buf;
+}
+
+// The cache file: {"<key>": {"engine": E, "tpa": T, "ms_per_step": M}, ...}
+static std::map<std::string, TuneChoice> read_cache(const char* path)
+{
+    std::map<std::string, TuneChoice> out;
+    std::ifstream f(path);
+    if (!f) return out;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string s = ss.str();
+    size_t p = 0;
+    for (;;) {
+        const size_t k0 = s.find('"', p);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = s.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const std::string key = s.substr(k0 + 1, k1 - k0 - 1);
+        const size_t b0 = s.find('{', k1), b1 = s.find('}', k1);
+        if (b0 == std::string::npos || b1 == std::string::npos || b0 > b1) break;
+        const std::string body = s.substr(b0, b1 - b0);
+        TuneChoice c{};
+        int ok = 0;
+        size_t q;
+        if ((q = body.find("\"engine\"")) != std::string::npos) ok += std::sscanf(body.c_str() + body.find(':', q) + 1, "%d", &c.engine);
+        if ((q = body.find("\"tpa\"")) != std::string::npos) ok += std::sscanf(body.c_str() + body.find(':', q) + 1, "%d", &c.tpa);
+        if ((q = body.find("\"ms_per_step\"")) != std::string::npos)
+            ok += std::sscanf(body.c_str() + body.find(':', q) + 1, "%lf", &c.ms);
+        if (ok == 3) out[key] = c;
+        p = b1 + 1;
+    }
+    return out;
+}
+
+static void write_cache(const char* path, const std::map<std::string, TuneChoice>& m)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    std::ofstream f(tmp);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : m) {
+        f << "  \"" << kv.first << "\": {\"engine\": " << kv.second.engine << ", \"tpa\": " << kv.second.tpa
+          << ", \"ms_per_step\": " << kv.second.ms << "}" << (++i < m.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+    f.close();
+    std::rename(tmp.c_str(), path);
+}
+
+bool tune_lookup(const char* path, const std::string& key, TuneChoice& out)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    auto it = g_mem.find(key);
+    if (it != g_mem.end()) {
+        out = it->second;
+        return true;
+    }
+    if (path) {
+        auto m = read_cache(path);
+        auto jt = m.find(key);
+        if (jt != m.end()) {
+            g_mem[key] = jt->second;
+            out = jt->second;
+            return true;
+        }
+    }
+    return false;
+}
+
+void tune_store(const char* path, const std::string& key, const TuneChoice& c)
+{
+    std::lock_guard<std::mutex> g(g_mu);
+    g_mem[key] = c;
+    if (path) {
+        auto m = read_cache(path);
+        m[key] = c;
+        write_cache(path, m);
+    }
+}
+
+// Time every candidate on a throwaway context of the same workload.
+int tune_run(int R, const int32_t* N, const double* T, double rho, double rc, double skin, double dt, int Nx,
+             uint64_t seed, const re_options& base, TuneChoice& best)
+{
+    std::vector<int> engines;
+    if (base.exchange_mode == RE_ASYNC)
+        engines = {RE_PERSISTENT};
+    else
+        engines = {RE_LOCKSTEP, RE_PERSISTENT};
+    best = TuneChoice{-1, 0, 1e300};
+    int last_err = RE_OK;
+    for (int eng : engines)
+        for (int tpa : {1, 2, 4, 8}) {
+            re_options o = base;
+            o.autotune = 0;
+            o.tune_cache = nullptr;
+            o.batched_engine = eng;
+            o.threads_per_atom = tpa;
+            o.log_capacity = 1 << 12;
+            re_ctx* c = nullptr;
+            int rc0 = re_create(&c, R, N, T, rho, rc, skin, dt, Nx, seed, &o);
+            if (rc0 != RE_OK) {
+                last_err = rc0;
+                continue;
+            }
+            double ms = 1e300;
+            // warm up, estimate, then time about a quarter of a second
+            using clk = std::chrono::steady_clock;
+            std::vector<double> Uq(R);  // a query synchronises the context's stream
+            bool ok = re_step(c, 4) == RE_OK;
+            auto t0 = clk::now();
+            ok = ok && re_step(c, 4) == RE_OK && re_query_energies(c, Uq.data()) == RE_OK;
+            const double est = std::chrono::duration<double, std::milli>(clk::now() - t0).count() / 4.0;
+            if (ok) {
+                const int k = std::max(8, std::min(400, (int)(250.0 / std::max(est, 1e-3))));
+                t0 = clk::now();
+                ok = re_step(c, k) == RE_OK && re_query_energies(c, Uq.data()) == RE_OK;
+                ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count() / k;
+            }
+            re_destroy(c);
+            if (ok && ms < best.ms) best = TuneChoice{eng, tpa, ms};
+        }
+    return best.engine < 0 ? (last_err ? last_err : RE_EDEVICE) : RE_OK;
+}
+
+}  // namespace re

@@ -37,7 +37,7 @@ class Options(C.Structure):
                 ("exchange_mode", C.c_int), ("rho_per_replica", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("watchdog_seconds", C.c_double),
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
-                ("team_size", C.c_int), ("tune_cache", C.c_char_p)]
+                ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int)]
 
 
 class XLogRec(C.Structure):
@@ -77,6 +77,7 @@ def lib():
         L.re_test_philox.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int, vp]
         L.re_test_normals.argtypes = [C.c_int, u64, vp, C.c_int, vp]
         L.re_profile.argtypes = [vp, C.c_int]
+        L.re_query_config.argtypes = [vp, vp, vp, vp]
         L.re_query_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.re_destroy.argtypes = [vp]
         L.re_destroy.restype = None
@@ -86,7 +87,7 @@ def lib():
                   "re_query_slots", "re_query_box", "re_query_acceptance", "re_query_steps",
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
-                  "re_profile", "re_query_kernel_time"):
+                  "re_profile", "re_query_kernel_time", "re_query_config"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -121,7 +122,7 @@ class Engine:
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
-                 tune_cache=None):
+                 tune_cache=None, autotune=False):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -145,6 +146,7 @@ class Engine:
         o.block_size = int(block_size)
         o.team_size = int(team_size)
         o.tune_cache = tune_cache.encode() if tune_cache else None
+        o.autotune = 1 if autotune else 0
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))
@@ -227,6 +229,14 @@ class Engine:
     def _n(self, r):
         # out-of-range replicas reach the library, which rejects them
         return int(self.N[r]) if 0 <= r < self.R else 0
+
+    def query_config(self):
+        """(engine, threads_per_atom, team_size) the context runs with."""
+        e = np.zeros(1, np.int32)
+        t = np.zeros(1, np.int32)
+        m = np.zeros(1, np.int32)
+        _check(lib().re_query_config(self._ctx, _ptr(e), _ptr(t), _ptr(m)), self._ctx)
+        return ("persistent" if e[0] == RE_PERSISTENT else "lockstep"), int(t[0]), int(m[0])
 
     def profile(self, enable):
         _check(lib().re_profile(self._ctx, int(enable)), self._ctx)
