@@ -56,6 +56,9 @@ extern "C" {
 /* exchange timing */
 #define RE_SYNC 0  /* attempt after every N_x steps of every replica */
 #define RE_ASYNC 1 /* rotating master triggers after N_x of its own steps */
+/* persistent engine team barrier */
+#define RE_BARRIER_AUTO 0  /* one-XCD release for teams that share an L2 */
+#define RE_BARRIER_AGENT 1 /* agent-scope release and acquire always */
 
 typedef struct re_ctx re_ctx; /* opaque; owned by the library until re_destroy */
 
@@ -83,6 +86,13 @@ typedef struct {
                                     workload (or take the choice from tune_cache);
                                     explicit engine/threads_per_atom settings are
                                     then ignored */
+    int team_barrier;            /* persistent engine's barrier between the
+                                    workgroups of one replica: RE_BARRIER_AUTO
+                                    (default) lets a team whose workgroups all
+                                    run on one XCD (read on the device) release
+                                    through their shared L2 without an L2
+                                    write-back; RE_BARRIER_AGENT always uses
+                                    agent-scope release and acquire          */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */

@@ -28,9 +28,14 @@ def hipcc():
     return h
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source (in parallel) and link libre_hip.so."""
-    objdir = os.path.join(HERE, "_build")
+def build(verbose: bool = False, defines=(), lib_path: str = LIB) -> str:
+    """Compile every source (in parallel) and link libre_hip.so.
+
+    ``defines`` adds preprocessor symbols (e.g. ``RE_PHASE_TIMERS`` for a
+    build with the persistent kernel's phase timers, written to another
+    ``lib_path``)."""
+    tag = "_".join(defines)
+    objdir = os.path.join(HERE, "_build" + ("_" + tag if tag else ""))
     os.makedirs(objdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
@@ -38,7 +43,7 @@ def build(verbose: bool = False) -> str:
         if not os.path.exists(path):
             continue
         obj = os.path.join(objdir, src + ".o")
-        cmd = [hipcc()] + FLAGS + ["-c", path, "-o", obj]
+        cmd = [hipcc()] + FLAGS + ["-D" + d for d in defines] + ["-c", path, "-o", obj]
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
         objs.append(obj)
     failed = []
@@ -53,10 +58,10 @@ def build(verbose: bool = False) -> str:
     if failed:
         msg = "\n\n".join(" ".join(c) + "\n" + o for c, o in failed)
         raise RuntimeError("HIP build failed:\n" + msg)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib_path + ".tmp%d" % os.getpid()
     subprocess.check_call([hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib_path)
+    return lib_path
 
 
 if __name__ == "__main__":

@@ -72,6 +72,7 @@ struct re_ctx {
     std::vector<int> team_of;    // team size chosen per replica
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
+    int bar_mode = 0;            // team barrier mode of the persistent engine
     // force-kernel timing with HIP events (re_profile)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs
@@ -555,6 +556,7 @@ static PersistArgs persist_args(re_ctx* c)
     pa.c1sq = c->c1 * c->c1;
     pa.log_cap = c->cfg.log_cap;
     pa.timeout = (uint64_t)(c->watchdog * 1e8);
+    pa.bar_mode = c->bar_mode;
     return pa;
 }
 
@@ -662,6 +664,8 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.batched_engine != RE_LOCKSTEP && o.batched_engine != RE_PERSISTENT)
         return fail(nullptr, RE_EINVAL, "bad batched_engine");
     if (o.exchange_mode != RE_SYNC && o.exchange_mode != RE_ASYNC) return fail(nullptr, RE_EINVAL, "bad exchange_mode");
+    if (o.team_barrier != RE_BARRIER_AUTO && o.team_barrier != RE_BARRIER_AGENT)
+        return fail(nullptr, RE_EINVAL, "bad team_barrier");
     if (o.threads_per_atom && o.threads_per_atom != 1 && o.threads_per_atom != 2 && o.threads_per_atom != 4 &&
         o.threads_per_atom != 8)
         return fail(nullptr, RE_EINVAL, "threads_per_atom must be 1, 2, 4 or 8");
@@ -707,6 +711,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     c->Nx = N_x;
     c->seed = seed;
     c->watchdog = o.watchdog_seconds > 0 ? o.watchdog_seconds : 10.0;
+    c->bar_mode = o.team_barrier == RE_BARRIER_AGENT ? 0 : 1;
     c->N.assign(N_atoms, N_atoms + R);
     c->Tl.assign(T_ladder, T_ladder + R);
     c->rho = rho_r;
@@ -853,6 +858,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(c->ps.beat, 1);
     ALLOC(c->ps.abort, 1);
     ALLOC(c->ps.err, 1);
+    ALLOC(c->ps.xmask, R);
     ALLOC(c->d_call, 1);
     ALLOC(c->d_target, R);
 #undef ALLOC

@@ -7,9 +7,10 @@
 // exchange joins happen when that replica needs them -- so replicas
 // progress at their own speed and may have taken different numbers of steps
 // between exchange attempts (Implementation section: asynchronous
-// iteration).  Team members synchronise through a counter barrier with
-// agent-scope release/acquire; the leader (member 0) runs the reorder, the
-// energy sum and the exchange protocol.
+// iteration).  Team members synchronise through a counter barrier (agent-
+// scope acquire; the release skips the L2 write-back when every member runs
+// on one XCD); the leader (member 0) runs the reorder, the energy sum and
+// the exchange protocol.
 //
 // Exchange protocol, attempt k (k0 = first attempt of the call):
 //   gate     every replica has resolved attempt k-1 (the "done" counter
@@ -39,6 +40,30 @@ __device__ __forceinline__ uint64_t clock100()
 {
     return __builtin_amdgcn_s_memrealtime();  // 100 MHz constant clock
 }
+
+// Optional phase timers (built with RE_PHASE_TIMERS): thread 0 of every
+// workgroup adds the 100 MHz ticks spent in each phase of k_persist to its
+// own row; re_debug_phase_ticks copies the rows out and clears them.
+#ifdef RE_PHASE_TIMERS
+constexpr int kPhases = 8;
+__device__ unsigned long long g_phase_ticks[1024 * kPhases];
+#define PT_INIT() uint64_t pt_last = clock100()
+#define PT_MARK(k)                                                  \
+    do {                                                            \
+        if (threadIdx.x == 0) {                                     \
+            const uint64_t pt_now = clock100();                     \
+            g_phase_ticks[blockIdx.x * kPhases + (k)] += pt_now - pt_last; \
+            pt_last = pt_now;                                       \
+        }                                                           \
+    } while (0)
+#else
+#define PT_INIT() \
+    do {          \
+    } while (0)
+#define PT_MARK(k) \
+    do {           \
+    } while (0)
+#endif
 
 // Bounded waiting (thread 0 of a workgroup).  The watchdog counts time
 // without progress: any completed force phase anywhere (the heartbeat)
@@ -86,18 +111,26 @@ __device__ bool wait_ge_i64(const PersistArgs& pa, const int64_t* p, int64_t v)
     return wait_ge_u64(pa, reinterpret_cast<const uint64_t*>(p), (uint64_t)v);
 }
 
-// Team barrier: a counter per team with agent-scope release/acquire (the
-// workgroups of a team may sit on different XCDs, whose L2s are not
-// coherent without the write-back/invalidate these fences imply).
-// Returns false when the run is being aborted.
-__device__ bool team_sync(const PersistArgs& pa, unsigned* ctr, unsigned& epoch, int t, int* s_ok)
+// Team barrier: a counter per team.  Mode agent (any placement):
+// agent-scope release/acquire around the counter, i.e. write-back of this
+// XCD's L2 and invalidation of L1 and L2 for lines of other XCDs.  Mode
+// one-XCD (every workgroup of the team reported the same XCC, so the team
+// shares one L2): release is each wave waiting for its own stores to
+// complete at the L2 (s_waitcnt 0) before the workgroup barrier -- no L2
+// write-back -- and acquire stays agent-scope.  Returns false when the run
+// is being aborted.
+__device__ bool team_sync(const PersistArgs& pa, unsigned* ctr, unsigned& epoch, int t, bool one_xcd, int* s_ok)
 {
+    if (one_xcd) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         int ok = 1;
         if (t > 1) {
             ++epoch;
-            __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            if (one_xcd)
+                __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else
+                __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
             const unsigned tgt = epoch * (unsigned)t;
             Watch w = watch_start(pa);
             while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < tgt) {
@@ -230,6 +263,19 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     const int i0 = min(rd.N, m * chunk), i1 = min(rd.N, i0 + chunk);
     const int tid = threadIdx.x, nt = blockDim.x;
     unsigned epoch = 0;
+    // which XCDs does the team run on?  Every member reports its XCC before
+    // a first agent-scope barrier; one XCC for all allows the one-XCD barrier
+    bool one_xcd = false;
+    if (t > 1) {
+        if (tid == 0) {
+            const unsigned xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | (3 << 11)) & 0xFu;  // HW_REG_XCC_ID
+            atomicOr(ps.xmask + pa.team_id[b], 1u << xcc);
+        }
+        if (!team_sync(pa, ctr, epoch, t, false, &sh[3])) return;
+        const unsigned msk =
+            __hip_atomic_load(ps.xmask + pa.team_id[b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        one_xcd = pa.bar_mode == 1 && __builtin_popcount(msk) == 1;
+    }
     // per-replica state, identical in every member
     int64_t s = d.steps[r];
     const int cur0 = cp.cur0;
@@ -263,6 +309,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 
     bool ok = true;
     int ctl = 0;
+    PT_INIT();
     while (ok) {
         // ---- at a stopped boundary s
         if (leader) {
@@ -328,18 +375,19 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             if (!ok) c = kCtlExit;
             if (tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = c;
         }
-        if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+        if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
             ok = false;
             break;
         }
         ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        PT_MARK(0);
         if (ctl & kCtlExit) break;
         // ---- first half of step s -> s+1
         {
             const bool apply = __hip_atomic_load(ps.apend + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             for (int i = i0 + tid; i < i1; i += nt) start_atom<P>(d, pa.sa, rd, r, i, cur, s, apply);
         }
-        if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+        if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
             ok = false;
             break;
         }
@@ -347,6 +395,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             d.alpha[r] = 1.0;
             ps.apend[r] = 0;
         }
+        PT_MARK(1);
         // ---- steps that end at a fused boundary loop here
         for (;;) {
             const int par = (int)((s + 1) & 1);
@@ -354,19 +403,21 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 __hip_atomic_load(d.flag + (size_t)par * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
             if (rebuild) {
                 if (leader) reorder_replica<P>(d, rd, r, cur, cnt, part);
-                if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+                if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
                     ok = false;
                     break;
                 }
+                PT_MARK(2);
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
                 for (int base = i0; base < i1; base += nt / kListLanes) {
                     const int i = base + tid / kListLanes;
                     list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M);
                 }
-                if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+                if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
                     ok = false;
                     break;
                 }
+                PT_MARK(3);
             }
             const bool stop = (ctl & kCtlStop) != 0;
             const int apb = nt / TPA;
@@ -378,10 +429,12 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     force_atom<P, kFused, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
             }
             if (leader && !stop && tid == 0) ps.ctl[(size_t)((s + 2) & 1) * R + r] = plan(s + 2);
-            if (!team_sync(pa, ctr, epoch, t, &sh[3])) {
+            PT_MARK(4);
+            if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
                 ok = false;
                 break;
             }
+            PT_MARK(5);
             if (leader && tid == 0) {
                 d.flag[(size_t)par * R + r] = 0u;
                 __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -392,6 +445,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     energy_replica<P>(d, rd, r, dpart);
                     Ucur = d.U[r];
                 }
+                PT_MARK(6);
                 join_pending = (ctl & kCtlJoin) != 0;
                 break;
             }
@@ -425,6 +479,7 @@ __global__ void k_persist_prepare(DevState d, PersistArgs pa, int nteams)
         ps.katt[i] = cp.k0;
     }
     if (i < 64 * nteams) pa.bar[i] = 0u;
+    if (i < nteams) ps.xmask[i] = 0u;
     if (i == 0) {
         *ps.xdone = 0ull;
         *ps.trig = (uint64_t)cp.k0;
@@ -456,6 +511,18 @@ hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, i
     if (e != hipSuccess) return e;
     return fp64 ? persist_t<PF64>(d, pa, nblk, st) : persist_t<PMixed>(d, pa, nblk, st);
 }
+
+#ifdef RE_PHASE_TIMERS
+extern "C" int re_debug_phase_ticks(unsigned long long* out, int nblk)
+{
+    if (nblk < 0 || nblk > 1024) return -1;
+    if (hipMemcpyFromSymbol(out, HIP_SYMBOL(g_phase_ticks), sizeof(unsigned long long) * kPhases * nblk) !=
+        hipSuccess)
+        return -3;
+    static unsigned long long zero[1024 * kPhases];
+    return hipMemcpyToSymbol(HIP_SYMBOL(g_phase_ticks), zero, sizeof zero) == hipSuccess ? 0 : -3;
+}
+#endif
 
 hipError_t persist_occupancy(bool fp64, int tpa, int* blocks_per_cu)
 {

@@ -25,6 +25,7 @@ struct PersistState {
     uint64_t* beat;     // progress heartbeat: force phases completed
     uint32_t* abort;    // nonzero: every team leaves
     uint32_t* err;      // kErr* bits
+    uint32_t* xmask;    // per team: XCDs its workgroups run on (per call)
 };
 
 // Per-call parameters, in device memory (updated before each launch).
@@ -50,6 +51,8 @@ struct PersistArgs {
     double c1sq;
     int64_t log_cap;
     uint64_t timeout;         // watchdog, in 100 MHz clock ticks without progress
+    int bar_mode;             // team barrier: 0 agent-scope release + acquire; 1 for teams on one
+                              // XCD: stores complete to the shared L2 + agent-scope acquire
 };
 
 hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, int nblk, int nteams, hipStream_t st);

@@ -20,6 +20,7 @@ RE_MIXED, RE_FP64 = 0, 1
 RE_BATCHED, RE_PLAIN = 0, 1
 RE_LOCKSTEP, RE_PERSISTENT = 0, 1
 RE_SYNC, RE_ASYNC = 0, 1
+RE_BARRIER_AUTO, RE_BARRIER_AGENT = 0, 1
 
 _ERRNAMES = {RE_EINVAL: "RE_EINVAL", RE_ENOMEM: "RE_ENOMEM", RE_EDEVICE: "RE_EDEVICE",
              RE_ETIMEOUT: "RE_ETIMEOUT", RE_ESTATE: "RE_ESTATE", RE_EOVERFLOW: "RE_EOVERFLOW"}
@@ -37,7 +38,8 @@ class Options(C.Structure):
                 ("exchange_mode", C.c_int), ("rho_per_replica", C.POINTER(C.c_double)),
                 ("stream", C.c_void_p), ("watchdog_seconds", C.c_double),
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
-                ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int)]
+                ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
+                ("team_barrier", C.c_int)]
 
 
 class XLogRec(C.Structure):
@@ -122,7 +124,7 @@ class Engine:
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
-                 tune_cache=None, autotune=False):
+                 tune_cache=None, autotune=False, team_barrier="auto"):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -147,6 +149,7 @@ class Engine:
         o.team_size = int(team_size)
         o.tune_cache = tune_cache.encode() if tune_cache else None
         o.autotune = 1 if autotune else 0
+        o.team_barrier = {"auto": RE_BARRIER_AUTO, "agent": RE_BARRIER_AGENT}[team_barrier]
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))

@@ -58,12 +58,15 @@ def test_persistent_sync_equals_lockstep(relib, precision, team):
 
 
 def test_team_sizes_agree(relib):
-    """Teams of 1, 3 and 8 workgroups per replica give the same run."""
+    """Teams of 1, 3 and 8 workgroups per replica, with either team barrier
+    (one-XCD release where the team shares an L2, or agent scope always),
+    give the same run."""
     R, N = 4, 3000
     T = W.ladder(0.8, 1.4, R)
     ref = None
-    for team in (1, 3, 8):
-        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 20, 2, team_size=team, watchdog_seconds=5)
+    for team, bar in ((1, "auto"), (3, "auto"), (8, "auto"), (8, "agent"), (3, "agent")):
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 20, 2, team_size=team, watchdog_seconds=5,
+                         team_barrier=bar)
         e.step(60)
         st = states(e, R)
         e.close()
