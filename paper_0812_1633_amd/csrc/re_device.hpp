@@ -118,6 +118,11 @@ struct PMixed {
     {
         return (int)__umulhi((uint32_t)x ^ 0x80000000u, (uint32_t)rd.ncell);
     }
+    // position in cell units, [0, ncell) (FP32: for conservative bounds only)
+    __device__ static float cellpos(int x, const RepDev& rd)
+    {
+        return (float)((uint32_t)x ^ 0x80000000u) * ((float)rd.ncell * 0x1p-32f);
+    }
     __device__ static real rc2(const RepDev& rd) { return rd.rc2f; }
     __device__ static real rl2(const RepDev& rd) { return rd.rl2f; }
     __device__ static real lim2(const RepDev& rd) { return rd.lim2f; }
@@ -155,6 +160,7 @@ struct PF64 {
         int c = (int)floor((x / rd.L + 0.5) * (double)rd.ncell);
         return c < 0 ? 0 : (c >= rd.ncell ? rd.ncell - 1 : c);
     }
+    __device__ static float cellpos(double x, const RepDev& rd) { return (float)((x / rd.L + 0.5) * (double)rd.ncell); }
     __device__ static real rc2(const RepDev& rd) { return rd.rc2d; }
     __device__ static real rl2(const RepDev& rd) { return rd.rl2d; }
     __device__ static real lim2(const RepDev& rd) { return rd.lim2d; }
@@ -302,131 +308,184 @@ __device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int 
     __syncthreads();
 }
 
+// Rows of the list build scanned by lane q of an LPA-lane group (nc >= 5):
+// the 25 rows (x offset major) dealt out so that every lane expects about
+// the same number of candidate cells after trimming (centre rows reach
+// about 4.6 cells, edge rows 2.6, corner rows 0.5).  -1: no row.  Packed as
+// 5 bits per lane per slot w.
+template <int LPA>
+struct ListRowSets;
+template <>
+struct ListRowSets<8> {
+    static constexpr int kRPL = 4;
+    static constexpr int8_t rows[8][4] = {{3, 12, 21, -1}, {0, 7, 10, 20}, {4, 11, 14, 24}, {5, 9, 13, -1},
+                                          {15, 17, 19, -1}, {6, 18, -1, -1}, {2, 8, 23, -1}, {1, 16, 22, -1}};
+};
+template <>
+struct ListRowSets<4> {
+    static constexpr int kRPL = 7;
+    static constexpr int8_t rows[4][7] = {{1, 5, 9, 12, 16, 22, -1}, {0, 7, 10, 15, 17, 19, 20},
+                                          {3, 6, 11, 18, 23, -1, -1}, {2, 4, 8, 13, 14, 21, 24}};
+};
+template <int LPA>
+__host__ __device__ constexpr uint64_t list_row_pack(int w)
+{
+    uint64_t v = 0;
+    for (int q = 0; q < LPA; ++q) v |= (uint64_t)(ListRowSets<LPA>::rows[q][w] & 31) << (5 * q);
+    return v;
+}
+// LDS words per lane that list_rows needs (range starts, slot offsets, end)
+template <int LPA>
+__host__ __device__ constexpr int list_lds_words()
+{
+    return 4 * ListRowSets<LPA>::kRPL + 1;
+}
+
 // Verlet list build on the fine cell grid (cell side >= half the list
 // radius, cells ordered z fastest): the candidates of an atom are the atoms
 // of the 5 x 5 x 5 cells around its own, i.e. 25 rows of 5 consecutive
 // cells, each row one or two contiguous slot ranges of the cell-sorted
-// arrays (all cells when there are fewer than 5 per side).  A group of LPA
-// lanes serves one atom, lane q scanning rows q, q + LPA, ...: it counts its
-// hits and keeps them as a bit mask, a shuffle scan over the group gives
-// each lane its first list entry, then the lane writes its hits.
-// Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa].
+// arrays (all nc^2 columns of nc cells when there are fewer than 5 cells
+// per side).  Every row is first trimmed to the atom's own position: it is
+// skipped when its column lies farther than the list radius in x-y, and
+// otherwise shortened to the z cells that reach within the radius
+// (conservative bounds with a 1e-4 margin: no pair within the list radius is
+// lost).  A group of LPA lanes serves one atom; lane q takes a fixed set of
+// rows and scans their candidates as one flat sequence, four in flight (the
+// slot of flat candidate k is k plus the offset of its range, found from a
+// bit mask of range starts and a small per-lane table in LDS).  Hits are
+// kept as a bit mask; a scan of the lane counts over the group places them,
+// so the list holds lane 0's hits, then lane 1's, ..., each in scan order.
+// Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa]
+// (tpa a power of two).  `lds`: list_lds_words<LPA>() words of this lane.
 template <class P, int LPA>
 __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int i,
-                                          bool act, int q, int tpa, int M)
+                                          bool act, int q, int tpa, int M, int* lds)
 {
     using real = typename P::real;
-    constexpr int RPL = (25 + LPA - 1) / LPA;  // rows per lane
+    constexpr int RPL = ListRowSets<LPA>::kRPL;
     const int nc = rd.ncell;
     const int32_t* cs = d.cell_start + rd.cell_base;
     const typename P::pos_t pi = pos[act ? i : 0];
-    // this lane's candidates: up to 2 RPL contiguous slot ranges
-    int sr[2 * RPL], er[2 * RPL];
-#pragma unroll
-    for (int k = 0; k < 2 * RPL; ++k) sr[k] = er[k] = 0;
+    // this lane's ranges: flat start lds[2 n], slot offset lds[2 n + 1]
+    int T = 0, nr = 0;
+    uint64_t bounds = 0;  // bit k: a range other than the first starts at flat index k
+    lds[1] = 0;           // offset used by a lane without candidates
+    auto add = [&](int a, int b) {
+        if (b > a) {
+            if (nr > 0 && T < 64) bounds |= 1ull << T;
+            lds[2 * nr] = T;
+            lds[2 * nr + 1] = a - T;
+            ++nr;
+            T += b - a;
+        }
+    };
     if (act) {
         const int cx = P::cellc(pi.x, rd), cy = P::cellc(pi.y, rd), cz = P::cellc(pi.z, rd);
+        // offsets inside the own cell, in cell units
+        const float fx = fminf(fmaxf(P::cellpos(pi.x, rd) - (float)cx, 0.f), 1.f);
+        const float fy = fminf(fmaxf(P::cellpos(pi.y, rd) - (float)cy, 0.f), 1.f);
+        const float fz = fminf(fmaxf(P::cellpos(pi.z, rd) - (float)cz, 0.f), 1.f);
 #pragma unroll
         for (int w = 0; w < RPL; ++w) {
-            const int row = q + w * LPA;
             if (nc >= 5) {
+                const int row = (int)((list_row_pack<LPA>(w) >> (5 * q)) & 31u);
                 if (row < 25) {
-                    const int x = (cx + row / 5 - 2 + nc) % nc, y = (cy + row % 5 - 2 + nc) % nc;
-                    const int rb = (x * nc + y) * nc;
-                    const int z0 = cz - 2, z1 = cz + 2;
-                    if (z0 < 0) {
-                        sr[2 * w] = cs[rb + z0 + nc];
-                        er[2 * w] = cs[rb + nc];
-                        sr[2 * w + 1] = cs[rb];
-                        er[2 * w + 1] = cs[rb + z1 + 1];
-                    } else if (z1 >= nc) {
-                        sr[2 * w] = cs[rb + z0];
-                        er[2 * w] = cs[rb + nc];
-                        sr[2 * w + 1] = cs[rb];
-                        er[2 * w + 1] = cs[rb + z1 - nc + 1];
-                    } else {
-                        sr[2 * w] = cs[rb + z0];
-                        er[2 * w] = cs[rb + z1 + 1];
+                    const int ox = row / 5 - 2, oy = row % 5 - 2;
+                    // distance from the atom to the row's column, in cell units
+                    const float ex = ox > 0 ? (float)ox - fx : (ox < 0 ? fx + (float)(-ox - 1) : 0.f);
+                    const float ey = oy > 0 ? (float)oy - fy : (oy < 0 ? fy + (float)(-oy - 1) : 0.f);
+                    const float h2 = rd.rlcell2 - ex * ex - ey * ey;
+                    if (h2 > 0.f) {
+                        int x = cx + ox, y = cy + oy;
+                        x += x < 0 ? nc : 0;
+                        x -= x >= nc ? nc : 0;
+                        y += y < 0 ? nc : 0;
+                        y -= y >= nc ? nc : 0;
+                        const int rb = (x * nc + y) * nc;
+                        const float h = sqrtf(h2);
+                        const int z0 = cz + max(-2, (int)floorf(fz - h)), z1 = cz + min(2, (int)floorf(fz + h));
+                        if (z0 < 0) {
+                            add(cs[rb + z0 + nc], cs[rb + nc]);
+                            add(cs[rb], cs[rb + z1 + 1]);
+                        } else if (z1 >= nc) {
+                            add(cs[rb + z0], cs[rb + nc]);
+                            add(cs[rb], cs[rb + z1 - nc + 1]);
+                        } else {
+                            add(cs[rb + z0], cs[rb + z1 + 1]);
+                        }
                     }
                 }
-            } else if (row < nc * nc) {
-                sr[2 * w] = cs[row * nc];
-                er[2 * w] = cs[row * nc + nc];
+            } else {
+                const int row = q + w * LPA;
+                if (row < nc * nc) add(cs[row * nc], cs[row * nc + nc]);
             }
         }
     }
-    int len = 0;
-#pragma unroll
-    for (int k = 0; k < 2 * RPL; ++k) len += er[k] - sr[k];
-    // candidate number k -> slot
-    auto slot_of = [&](int k) {
-        int j = i;
-#pragma unroll
-        for (int r = 0; r < 2 * RPL; ++r) {
-            const int n = er[r] - sr[r];
-            if (k >= 0 && k < n) j = sr[r] + k;
-            k -= n;
-        }
-        return j;
-    };
+    lds[2 * nr] = T;
     const real rl2 = P::rl2(rd);
-    uint64_t mask0 = 0, mask1 = 0;
+    // flat candidate k -> slot
+    auto slot = [&](int k) {
+        const int ri = __popcll(bounds & ((2ull << k) - 1ull));
+        return k + lds[2 * ri + 1];
+    };
+    auto test = [&](const typename P::pos_t& pj, int j) {
+        real dx, dy, dz;
+        P::diff(pi, pj, rd, dx, dy, dz);
+        // bitwise, so that no load is moved under a branch
+        return (dx * dx + dy * dy + dz * dz < rl2) & (j != i);
+    };
+    const int T64 = T < 64 ? T : 64;
+    uint64_t mk = 0;
     int cnt = 0;
-    // four candidates in flight per lane
-    for (int k0 = 0; k0 < len; k0 += 4) {
+    for (int k0 = 0; k0 < T64; k0 += 4) {
         typename P::pos_t pj[4];
         int jj[4];
+        // without branches: a candidate past the end reads an in-range slot
+        // and is masked out of the test
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            jj[u] = k0 + u < len ? slot_of(k0 + u) : i;
-            pj[u] = pos[jj[u]];
-        }
+        for (int u = 0; u < 4; ++u) jj[u] = min(max(slot(k0 + u), 0), rd.N - 1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) pj[u] = pos[jj[u]];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + u;
-            real dx, dy, dz;
-            P::diff(pi, pj[u], rd, dx, dy, dz);
-            if (k < len && dx * dx + dy * dy + dz * dz < rl2 && jj[u] != i) {
-                if (k < 64)
-                    mask0 |= 1ull << k;
-                else if (k < 128)
-                    mask1 |= 1ull << (k - 64);
-                ++cnt;
-            }
+            const bool hit = (k < T64) & test(pj[u], jj[u]);
+            mk |= hit ? (1ull << k) : 0ull;
+            cnt += hit ? 1 : 0;
         }
     }
-    int off = cnt;
-    for (int m = 1; m < LPA; m <<= 1) {
-        const int v = __shfl_up(off, m, LPA);
-        if (q >= m) off += v;
+    // candidates past the mask (only with very full rows): walk the ranges
+    auto walk = [&](auto&& on_hit) {
+        for (int n = 0; n < nr; ++n) {
+            const int k1 = lds[2 * n + 2], off = lds[2 * n + 1];
+            for (int k = max(lds[2 * n], 64); k < k1; ++k)
+                if (test(pos[k + off], k + off)) on_hit(k + off);
+        }
+    };
+    if (T > 64) walk([&](int) { ++cnt; });
+    // first entry of this lane: the hits of the lanes before it
+    int incl = cnt;
+#pragma unroll
+    for (int sft = 1; sft < LPA; sft <<= 1) {
+        const int v = __shfl_up(incl, sft, LPA);
+        if (q >= sft) incl += v;
     }
-    const int tot = __shfl(off, LPA - 1, LPA);
-    off -= cnt;
+    const int tot = __shfl(incl, LPA - 1, LPA);
+    int o = incl - cnt;
     uint32_t* nl = d.nl + rd.nl_base;
     const size_t Np = (size_t)rd.Np;
+    const int lg = __ffs(tpa) - 1;
     auto put = [&](int j) {
-        if (off < M) nl[((size_t)(off / tpa) * Np + i) * tpa + (off % tpa)] = (uint32_t)j;
-        ++off;
+        if (o < M) nl[((size_t)(o >> lg) * Np + i) * tpa + (o & (tpa - 1))] = (uint32_t)j;
+        ++o;
     };
-    if (len <= 128) {
-        while (mask0) {
-            const int k = __builtin_ctzll(mask0);
-            mask0 &= mask0 - 1;
-            put(slot_of(k));
-        }
-        while (mask1) {
-            const int k = __builtin_ctzll(mask1);
-            mask1 &= mask1 - 1;
-            put(slot_of(k + 64));
-        }
-    } else {
-        for (int k = 0; k < len; ++k) {
-            const int j = slot_of(k);
-            real dx, dy, dz;
-            P::diff(pi, pos[j], rd, dx, dy, dz);
-            if (dx * dx + dy * dy + dz * dz < rl2 && j != i) put(j);
-        }
+    while (mk) {
+        const int k = __builtin_ctzll(mk);
+        mk &= mk - 1;
+        put(slot(k));
     }
+    if (T > 64) walk(put);
     if (act && q == 0) {
         d.nn[rd.base + i] = tot < M ? tot : M;
         if (tot > M) atomicOr(d.overflow, 1u);

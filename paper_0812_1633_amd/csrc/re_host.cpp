@@ -752,6 +752,10 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         int nc = (int)std::floor(rd.L / (0.5 * rlist * (1.0 + 1e-5)));
         nc = std::max(1, std::min(nc, kMaxCellsPerSide));
         rd.ncell = nc;
+        {
+            const double q = rlist * (1.0 + 1e-4) * nc / rd.L;
+            rd.rlcell2 = (float)(q * q);
+        }
         rd.cell_base = cells;
         cells += nc * nc * nc + 1;
         c->cells_max = std::max(c->cells_max, nc * nc * nc);

@@ -10,7 +10,10 @@ namespace re {
 constexpr int kMaxCellsPerSide = 32;               // cell grid cap (cells may exceed r_list/2)
 constexpr int kMaxCells = kMaxCellsPerSide * kMaxCellsPerSide * kMaxCellsPerSide;
 constexpr int kReorderThreads = 1024;              // one workgroup per replica
-constexpr int kListLanes = 8;                      // list-build lanes per atom (fixes the list order)
+#ifndef RE_LIST_LANES
+#define RE_LIST_LANES 8
+#endif
+constexpr int kListLanes = RE_LIST_LANES;          // list-build lanes per atom (4 or 8)
 constexpr int kListSlackRows = 8;                  // list rows read past a replica's block by the
                                                    // force loop's prefetch (values unused)
 constexpr uint32_t kPurposeInitVel = 0u;           // Philox counter word 3 ("purpose")
@@ -29,7 +32,7 @@ struct RepDev {
     int32_t cell_base;  // first entry of this replica in the cell arrays (ncell^3 + 1 entries)
     int64_t nl_base;    // first element of this replica's neighbour list
     int32_t Np;         // N rounded up to a multiple of 64 (list row length)
-    int32_t pad0;
+    float rlcell2;      // (list radius / cell side)^2 with a 1e-4 margin: row trimming
     double L;           // box side
     double s;           // length of one pair unit (mixed: L 2^-32; FP64: 1)
     double inv_s;       // 1 / s

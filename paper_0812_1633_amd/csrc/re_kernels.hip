@@ -36,13 +36,16 @@ template <class P>
 __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
 {
     constexpr int APB = 256 / kListLanes;  // atoms per block
+    constexpr int W = list_lds_words<kListLanes>();
+    __shared__ int lds[256 * W];
     const int r = sa.r0 + blockIdx.y;
     if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
     const RepDev rd = d.rep[r];
     const int i = blockIdx.x * APB + (int)(threadIdx.x / kListLanes);
     if ((int)blockIdx.x * APB >= rd.N) return;
     const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
-    list_rows<P, kListLanes>(d, rd, pos, i, i < rd.N, (int)(threadIdx.x % kListLanes), sa.tpa, sa.M);
+    list_rows<P, kListLanes>(d, rd, pos, i, i < rd.N, (int)(threadIdx.x % kListLanes), sa.tpa, sa.M,
+                             lds + threadIdx.x * W);
 }
 
 // Force + epilogue; the first block of each replica also marks the list of

@@ -245,7 +245,8 @@ constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4;
 template <class P, int TPA>
 __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 {
-    __shared__ int cnt[kMaxCells + 1];
+    __shared__ int cnt[kMaxCells + 1];  // reorder counts; list-build tables between reorders
+    static_assert(1024 * list_lds_words<kListLanes>() <= kMaxCells + 1, "list tables exceed the LDS array");
     __shared__ int part[1024];
     __shared__ double dpart[1024];
     __shared__ int sh[4];
@@ -411,7 +412,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
                 for (int base = i0; base < i1; base += nt / kListLanes) {
                     const int i = base + tid / kListLanes;
-                    list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M);
+                    list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
+                                             cnt + tid * list_lds_words<kListLanes>());
                 }
                 if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
                     ok = false;
