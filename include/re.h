@@ -45,6 +45,13 @@ extern "C" {
 
 /* thermostat */
 #define RE_LANGEVIN 0 /* BAOAB Langevin, friction gamma (gamma = 0: velocity Verlet, NVE) */
+#define RE_SVR 1      /* velocity Verlet + stochastic velocity rescaling (the thermostat of the
+                         Example section; Bussi, Donadio, Parrinello, J. Chem. Phys. 126,
+                         014101 (2007)): once per step, at the step boundary, every velocity
+                         of a replica is multiplied by sqrt(K'/K), K' drawn from the
+                         rescale's exact update with N_f = 3N - 3 and relaxation time
+                         svr_tau; gamma is ignored.  Every step then ends at a stopped
+                         boundary (no fused steps): slower than Langevin. */
 /* precision / form */
 #define RE_MIXED 0 /* positions as 32-bit periodic fixed point, FP32 pair arithmetic,
                       FP32 velocities; FP64 energy sums and rescale factors */
@@ -64,7 +71,7 @@ typedef struct re_ctx re_ctx; /* opaque; owned by the library until re_destroy *
 
 /* Optional settings.  A zero-initialised struct (or NULL) means defaults. */
 typedef struct {
-    int thermostat;              /* RE_LANGEVIN (only value)                      */
+    int thermostat;              /* RE_LANGEVIN (default) | RE_SVR                */
     double gamma;                /* Langevin friction; 0 selects NVE. Default: when
                                     gamma_set == 0, gamma = 1.0                   */
     int gamma_set;               /* nonzero: use the gamma field as given          */
@@ -93,6 +100,7 @@ typedef struct {
                                     through their shared L2 without an L2
                                     write-back; RE_BARRIER_AGENT always uses
                                     agent-scope release and acquire          */
+    double svr_tau;              /* RE_SVR relaxation time (LJ units); 0: 0.5     */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */
@@ -171,7 +179,10 @@ int re_query_exchange_log(re_ctx* ctx, re_xlog_rec* buf, int64_t cap, int64_t* n
                           int64_t* n_total);
 
 /* Positions (wrapped into [-L/2, L/2)) and full-step velocities of replica r
- * in atom-id order (3N doubles each; either pointer may be NULL). */
+ * in atom-id order (3N doubles each; either pointer may be NULL).  The
+ * velocities are those after every rescale of the current step boundary
+ * (exchange factor sqrt(T_new/T_old), thermostat rescale), even where the
+ * device applies the factor only with the next step. */
 int re_get_state(re_ctx* ctx, int r, double* x, double* v);
 
 /* Replace positions and velocities of replica r (atom-id order, 3N doubles

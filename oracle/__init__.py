@@ -76,7 +76,12 @@ def lib():
         L.oracle_md.argtypes = [C.c_int32, C.c_double, C.c_double, C.c_double, C.c_double,
                                 C.c_double, C.c_double, C.c_uint64, C.c_int32, C.c_int64,
                                 C.c_int64, dp, dp, dp, dp, C.POINTER(C.c_int64),
-                                C.POINTER(C.c_double), C.c_int]
+                                C.POINTER(C.c_double), C.c_int, C.c_int, C.c_double]
+        L.oracle_svr_factor.argtypes = [C.c_double] * 6
+        L.oracle_svr_factor.restype = C.c_double
+        L.oracle_svr_noise.argtypes = [C.c_uint64, C.c_int32, C.c_int32, C.c_int64,
+                                       C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.oracle_svr_noise.restype = None
         L.oracle_md.restype = C.c_int
         L.oracle_metropolis.argtypes = [C.c_double] * 5
         L.oracle_metropolis.restype = C.c_int
@@ -84,7 +89,8 @@ def lib():
                                       dp, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
         L.oracle_exchange.restype = C.c_int
         L.oracle_run.argtypes = [C.c_int32, i32p, i64p, dp, dp, C.c_double, C.c_double, C.c_double,
-                                 C.c_double, C.c_uint64, C.c_int, dp, dp, dp, dp, i64p, dp, i64p,
+                                 C.c_double, C.c_int, C.c_double, C.c_uint64, C.c_int, dp, dp, dp,
+                                 dp, i64p, dp, i64p,
                                  i32p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_int64,
                                  i64p, i64p, C.c_void_p, C.POINTER(C.c_int64)]
         L.oracle_run.restype = C.c_int
@@ -156,6 +162,27 @@ def force_on(x, L, rc, i):
     return F, e.value
 
 
+THERMOSTATS = {"langevin": 0, "svr": 1}
+SVR_TAU = 0.5  # relaxation time of the velocity rescale (the paper gives none)
+
+
+def svr_factor(K, Kbar, Nf, c, R1, S):
+    """Velocity factor sqrt(K'/K) of one stochastic velocity rescale
+    (Bussi, Donadio, Parrinello 2007; the Example section's thermostat):
+    R1 standard normal, S chi-square with N_f - 1 degrees of freedom,
+    c = exp(-dt/tau)."""
+    return lib().oracle_svr_factor(float(K), float(Kbar), float(Nf), float(c), float(R1), float(S))
+
+
+def svr_noise(seed, N, replica, step):
+    """(R1, S) of the rescale of `replica` at step boundary `step`: Philox
+    normals of counter (atom id, step, replica, purpose 4)."""
+    R1 = C.c_double()
+    S = C.c_double()
+    lib().oracle_svr_noise(seed, int(N), int(replica), int(step), C.byref(R1), C.byref(S))
+    return R1.value, S.value
+
+
 def metropolis(Ua, Ub, Tj, Tj1, u):
     """Metropolis decision for swapping T_j (held by a) and T_{j+1} (held by
     b) (Implementation section)."""
@@ -182,14 +209,18 @@ class Replica:
         return self.x.size // 3
 
 
-def md(rep: Replica, nsteps, skin, dt, gamma, T, seed, replica_id, use_list=True):
-    """Advance one replica ``nsteps`` BAOAB Langevin steps (Example section:
-    dt, thermostat; list update at half the skin)."""
+def md(rep: Replica, nsteps, skin, dt, gamma, T, seed, replica_id, use_list=True, thermostat="langevin",
+       tau=SVR_TAU):
+    """Advance one replica ``nsteps`` steps (Example section: dt, thermostat;
+    list update at half the skin): BAOAB Langevin with friction ``gamma``, or
+    velocity Verlet with the stochastic velocity rescale of relaxation time
+    ``tau`` (thermostat="svr")."""
     nreb = C.c_int64(rep.rebuilds)
     U = C.c_double(rep.U)
     rc = lib().oracle_md(rep.N, rep.L, rep.rc, float(skin), float(dt), float(gamma), float(T),
                          seed, int(replica_id), int(rep.step), int(nsteps), rep.x, rep.v,
-                         rep.F, rep.xref, C.byref(nreb), C.byref(U), int(use_list))
+                         rep.F, rep.xref, C.byref(nreb), C.byref(U), int(use_list),
+                         THERMOSTATS[thermostat], float(tau))
     if rc:
         raise RuntimeError("oracle_md failed: %d" % rc)
     rep.rebuilds = nreb.value
@@ -218,7 +249,8 @@ class Ensemble:
     """All replicas of a replica-exchange run, concatenated in replica order
     (each replica's atoms in atom-id order)."""
 
-    def __init__(self, N, L, Tl, rc, skin, dt, gamma, seed, x=None, v=None, use_list=True):
+    def __init__(self, N, L, Tl, rc, skin, dt, gamma, seed, x=None, v=None, use_list=True,
+                 thermostat="langevin", tau=SVR_TAU):
         self.N = np.ascontiguousarray(N, np.int32)
         self.R = len(self.N)
         self.off = np.zeros(self.R, np.int64)
@@ -228,6 +260,7 @@ class Ensemble:
         self.rc, self.skin, self.dt, self.gamma = float(rc), float(skin), float(dt), float(gamma)
         self.seed = int(seed)
         self.use_list = int(use_list)
+        self.thermostat, self.tau = THERMOSTATS[thermostat], float(tau)
         self.slot = np.arange(self.R, dtype=np.int32)
         tot = int(3 * self.N.astype(np.int64).sum())
         if x is None:
@@ -267,7 +300,8 @@ class Ensemble:
         recs = (XRec * max(1, cap))()
         n = C.c_int64(0)
         rc = lib().oracle_run(self.R, self.N, self.off, self.L, self.Tl, self.rc, self.skin,
-                              self.dt, self.gamma, self.seed, self.use_list, self.x, self.v,
+                              self.dt, self.gamma, self.thermostat, self.tau, self.seed,
+                              self.use_list, self.x, self.v,
                               self.F, self.xref, self.steps, self.U, self.rebuilds, self.slot,
                               int(nsteps), int(Nx),
                               None if sched is None else sched.ctypes.data, int(A), int(k0),

@@ -19,6 +19,10 @@
  *     single and double precision;
  *   - truncated-and-shifted LJ energy, plain truncated force (strict r < r_c);
  *   - BAOAB Langevin splitting (velocity-Verlet core, gamma = 0 is NVE);
+ *   - stochastic velocity rescaling (the thermostat the Example section
+ *     names): velocity Verlet, then once per step the rescale of Bussi,
+ *     Donadio and Parrinello with N_f = 3N - 3, relaxation time tau (0.5 by
+ *     default; the paper gives none) and the positive root;
  *   - Verlet list to r_c + skin rebuilt when one displacement exceeds skin/2
  *     (strict >), measured from the positions at the last rebuild;
  *   - exchange pattern alternates even/odd ladder pairs; "lowest rank" is the
@@ -37,6 +41,10 @@
 #define ORACLE_PURPOSE_OSTEP 1u
 #define ORACLE_PURPOSE_EXCHANGE 2u
 #define ORACLE_PURPOSE_VACANCY 3u
+#define ORACLE_PURPOSE_SVR 4u
+
+#define ORACLE_LANGEVIN 0
+#define ORACLE_SVR 1
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 counter-based generator, from its published definition:
@@ -395,16 +403,70 @@ static int needs_rebuild(int32_t N, double L, double skin, const double* x, cons
 }
 
 /* ------------------------------------------------------------------------ */
+/* Stochastic velocity rescaling (Example section: the thermostat; G. Bussi,
+ * D. Donadio, M. Parrinello, J. Chem. Phys. 126, 014101 (2007)).  Over a
+ * time dt the kinetic energy K relaxes towards Kbar = N_f T / 2 with time
+ * constant tau plus a noise term chosen so that K samples the canonical
+ * distribution (Gamma with shape N_f/2 and scale T):
+ *   K' = K + (1 - c) (Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
+ * c = exp(-dt / tau), R1 a standard normal and S a chi-square variate with
+ * N_f - 1 degrees of freedom; the velocities are multiplied by
+ * sqrt(K' / K) (the positive root).  K = 0 leaves them unchanged.           */
+double oracle_svr_factor(double K, double Kbar, double Nf, double c, double R1, double S)
+{
+    if (!(K > 0.0)) return 1.0;
+    double Knew = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
+    return sqrt(Knew / K);
+}
+
+/* The normals of the rescale of replica r at step boundary s: Philox
+ * counter (atom id, s, r, purpose 4) gives three normals per atom.  R1 is
+ * the first normal of atom 0; S is the sum of the squares of all others
+ * except the last two of atom 0 and the first of atom 1, i.e. 3N - 4 =
+ * N_f - 1 squared standard normals (a chi-square variate by definition).   */
+void oracle_svr_noise(uint64_t seed, int32_t N, int32_t replica, int64_t s, double* R1, double* S)
+{
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) {
+        double z[3];
+        oracle_normals3(seed, (uint32_t)i, (uint32_t)s, (uint32_t)replica, ORACLE_PURPOSE_SVR, z);
+        if (i == 0) {
+            *R1 = z[0];
+        } else if (i == 1) {
+            acc += z[1] * z[1] + z[2] * z[2];
+        } else {
+            acc += z[0] * z[0] + z[1] * z[1] + z[2] * z[2];
+        }
+    }
+    *S = acc;
+}
+
+/* One rescale of replica r at step boundary s (temperature T). */
+static void svr_rescale(int32_t N, double* v, double T, double c, uint64_t seed, int32_t replica, int64_t s)
+{
+    double K = 0.0;
+    for (int i = 0; i < 3 * N; ++i) K += 0.5 * v[i] * v[i];
+    const double Nf = 3.0 * N - 3.0;
+    double R1, S;
+    oracle_svr_noise(seed, N, replica, s, &R1, &S);
+    const double a = oracle_svr_factor(K, 0.5 * Nf * T, Nf, c, R1, S);
+    for (int i = 0; i < 3 * N; ++i) v[i] *= a;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Molecular dynamics of one replica (Example section: time step dt, the
- * temperature held by a thermostat).  The paper's thermostat is stochastic
- * velocity rescaling; this engine runs Langevin dynamics with friction gamma
- * in the BAOAB splitting (B. Leimkuhler, C. Matthews, Appl. Math. Res.
- * Express 2013), m = 1, h = dt/2, c1 = exp(-gamma dt),
+ * temperature held by a thermostat).  thermostat ORACLE_LANGEVIN: Langevin
+ * dynamics with friction gamma in the BAOAB splitting (B. Leimkuhler,
+ * C. Matthews, Appl. Math. Res. Express 2013), m = 1, h = dt/2,
+ * c1 = exp(-gamma dt),
  * c2 = sqrt((1 - c1^2) T):
  *     v += h F;  x += h v;  v = c1 v + c2 xi;  x += h v;  wrap;
  *     [list update if triggered];  F = F(x);  v += h F.
  * xi for atom id i at the step leaving step count s is the Box-Muller
  * triple of Philox counter (i, s, replica, purpose 1).
+ * thermostat ORACLE_SVR (the paper's thermostat): the same steps without O
+ * (c1 = 1, c2 = 0), then at each new step boundary s + 1 the stochastic
+ * velocity rescale above with c = exp(-dt / tau).
  *
  * State on entry: x, v at a step boundary, F = forces at x, xref = positions
  * at the last list update.  step0 = steps already done.  Runs nsteps steps,
@@ -415,11 +477,13 @@ static int needs_rebuild(int32_t N, double L, double skin, const double* x, cons
 int oracle_md(int32_t N, double L, double rc, double skin, double dt, double gamma, double T,
               uint64_t seed, int32_t replica, int64_t step0, int64_t nsteps,
               double* x, double* v, double* F, double* xref,
-              int64_t* rebuilds, double* U, int use_list)
+              int64_t* rebuilds, double* U, int use_list, int thermostat, double tau)
 {
     const double h = 0.5 * dt;
-    const double c1 = exp(-gamma * dt);
-    const double c2 = sqrt((1.0 - c1 * c1) * T);
+    const int svr = thermostat == ORACLE_SVR;
+    const double c1 = svr ? 1.0 : exp(-gamma * dt);
+    const double c2 = svr ? 0.0 : sqrt((1.0 - c1 * c1) * T);
+    const double csvr = svr ? exp(-dt / tau) : 1.0;
     vlist vl = {NULL, NULL, 0};
     double u = 0.0;
     int rc_ok = 0;
@@ -428,8 +492,8 @@ int oracle_md(int32_t N, double L, double rc, double skin, double dt, double gam
     }
     for (int64_t s = step0; s < step0 + nsteps; ++s) {
         for (int i = 0; i < N; ++i) {
-            double z[3];
-            oracle_normals3(seed, (uint32_t)i, (uint32_t)s, (uint32_t)replica, ORACLE_PURPOSE_OSTEP, z);
+            double z[3] = {0.0, 0.0, 0.0};
+            if (!svr) oracle_normals3(seed, (uint32_t)i, (uint32_t)s, (uint32_t)replica, ORACLE_PURPOSE_OSTEP, z);
             for (int k = 0; k < 3; ++k) {
                 double vi = v[3 * i + k] + h * F[3 * i + k];
                 double xi = x[3 * i + k] + h * vi;
@@ -449,6 +513,7 @@ int oracle_md(int32_t N, double L, double rc, double skin, double dt, double gam
         else
             oracle_forces(N, L, rc, x, F, &u, NULL);
         for (int i = 0; i < 3 * N; ++i) v[i] += h * F[i];
+        if (svr) svr_rescale(N, v, T, csvr, seed, replica, s + 1);
     }
     if (nsteps > 0) *U = u;
     vlist_free(&vl);
@@ -536,7 +601,8 @@ int oracle_exchange(int32_t R, const double* Tl, int32_t* slot, const double* U,
  * rebuilds[r], slot[r].  At an attempt the velocities of every replica are
  * multiplied by its factor.  attempts/accepts are per ladder pair (R - 1).  */
 int oracle_run(int32_t R, const int32_t* N, const int64_t* off, const double* L, const double* Tl,
-               double rc, double skin, double dt, double gamma, uint64_t seed, int use_list,
+               double rc, double skin, double dt, double gamma, int thermostat, double tau,
+               uint64_t seed, int use_list,
                double* x, double* v, double* F, double* xref,
                int64_t* steps, double* U, int64_t* rebuilds, int32_t* slot,
                int64_t nsteps, int32_t Nx, const int64_t* sched, int64_t A, int64_t k0,
@@ -576,7 +642,7 @@ int oracle_run(int32_t R, const int32_t* N, const int64_t* off, const double* L,
             int64_t n = target[r] - steps[r];
             int e = oracle_md(N[r], L[r], rc, skin, dt, gamma, Tr, seed, r, steps[r], n,
                               x + off[r], v + off[r], F + off[r], xref + off[r],
-                              &rebuilds[r], &U[r], use_list);
+                              &rebuilds[r], &U[r], use_list, thermostat, tau);
             if (e) err = e;
             steps[r] = target[r];
         }

@@ -179,8 +179,9 @@ __device__ __forceinline__ void set_xyz(typename P::vel_t& v, typename P::real x
 // Phase functions.  Each works on a range of atoms (or a whole replica) of
 // replica r; the lockstep kernels and the persistent engine call them.
 
-// First half of a step from a stopped boundary (B A O A of BAOAB) for atom
-// slot i:  v = alpha v + h F;  x += h v;  v = c1 v + c2 xi;  x += h v;
+// First half of a step from a stopped boundary (B A O A of BAOAB; B A A
+// without O under the velocity rescale) for atom slot i:
+// v = alpha v + h F;  x += h v;  v = c1 v + c2 xi;  x += h v;
 // then the half-skin test against x_ref, which sets the update flag of the
 // next step's parity.  xi: Philox counter (atom id, step, replica, 1).
 template <class P>
@@ -199,16 +200,18 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     const real c2 = (real)d.c2[r];
     real vx = a * v.x + hh * f.x, vy = a * v.y + hh * f.y, vz = a * v.z + hh * f.z;
     x = P::drift(x, hh * vx, hh * vy, hh * vz, rd);
-    const uint4 w = draw(sa.seed, (uint32_t)P::id(x), (uint32_t)step, (uint32_t)r, kPurposeOStep);
-    real z0, z1, z2;
-    if constexpr (P::kF64) {
-        normals3d(w, z0, z1, z2);
-    } else {
-        normals3f(w, z0, z1, z2);
+    if (sa.thermo == kThermoLangevin) {
+        const uint4 w = draw(sa.seed, (uint32_t)P::id(x), (uint32_t)step, (uint32_t)r, kPurposeOStep);
+        real z0, z1, z2;
+        if constexpr (P::kF64) {
+            normals3d(w, z0, z1, z2);
+        } else {
+            normals3f(w, z0, z1, z2);
+        }
+        vx = c1 * vx + c2 * z0;
+        vy = c1 * vy + c2 * z1;
+        vz = c1 * vz + c2 * z2;
     }
-    vx = c1 * vx + c2 * z0;
-    vy = c1 * vy + c2 * z1;
-    vz = c1 * vz + c2 * z2;
     x = P::drift(x, hh * vx, hh * vy, hh * vz, rd);
     pos[g] = x;
     set_xyz<P>(v, vx, vy, vz);
@@ -653,17 +656,76 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
 // Potential energy of replica r in FP64 with the whole workgroup: fixed-
 // order strided sums of the per-atom energies, then a fixed tree;
 // U = (1/2) sum_i e_i.  part: blockDim doubles of LDS.
+// Replica reductions sum over kRedWidth fixed slices (atom slots i = q mod
+// kRedWidth, in slot order) and then a fixed pairwise tree, so the result
+// does not depend on the workgroup size (the lockstep and the persistent
+// engine give the same bits).
+constexpr int kRedWidth = 256;
+
+// Stochastic velocity rescale of replica r at step boundary s (Example
+// section: the thermostat; Bussi, Donadio and Parrinello 2007), run by one
+// workgroup (part: 2 kRedWidth doubles): K = sum v^2 / 2 and the chi-square sum S of N_f - 1 = 3N - 4
+// squared normals (Philox counter (atom id, s, r, purpose 4): all three
+// normals of every atom but the first normal of atom 0, which is R1, its
+// other two and the first of atom 1), both in FP64; then
+//   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
+// Kbar = N_f T / 2 at the replica's temperature, and the pending velocity
+// factor is multiplied by sqrt(K'/K) (K = 0: unchanged).
+template <class P>
+__device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int cur, int64_t s, uint64_t seed,
+                            double c, double* part)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const typename P::vel_t* v = P::vel(d) + rd.base;
+    const typename P::pos_t* x = P::pos(d, cur) + rd.base;  // for the atom ids
+    for (int q = tid; q < kRedWidth; q += nt) {
+        double k2 = 0.0, chi = 0.0;
+        for (int i = q; i < rd.N; i += kRedWidth) {
+            const typename P::vel_t vi = v[i];
+            k2 += (double)vi.x * (double)vi.x + (double)vi.y * (double)vi.y + (double)vi.z * (double)vi.z;
+            const int id = P::id(x[i]);
+            double z0, z1, z2;
+            normals3d(draw(seed, (uint32_t)id, (uint32_t)s, (uint32_t)r, kPurposeSVR), z0, z1, z2);
+            chi += (id == 0 ? 0.0 : (id == 1 ? 0.0 : z0 * z0)) + (id == 0 ? 0.0 : z1 * z1 + z2 * z2);
+        }
+        part[q] = k2;
+        part[kRedWidth + q] = chi;
+    }
+    __syncthreads();
+    for (int off = kRedWidth >> 1; off > 0; off >>= 1) {
+        for (int q = tid; q < off; q += nt) {
+            part[q] += part[q + off];
+            part[kRedWidth + q] += part[kRedWidth + q + off];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const double K = 0.5 * part[0], S = part[kRedWidth];
+        double R1, z1, z2;
+        normals3d(draw(seed, 0u, (uint32_t)s, (uint32_t)r, kPurposeSVR), R1, z1, z2);
+        const double Nf = 3.0 * rd.N - 3.0;
+        const double Kbar = 0.5 * Nf * d.Tl[d.slot[r]];
+        if (K > 0.0) {
+            const double Kn = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
+            d.alpha[r] *= sqrt(Kn / K);
+        }
+    }
+    __syncthreads();
+}
+
 template <class P>
 __device__ void energy_replica(const DevState& d, const RepDev& rd, int r, double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    double s = 0.0;
     const typename P::real* e = P::epot(d) + rd.base;
-    for (int i = tid; i < rd.N; i += nt) s += (double)e[i];
-    part[tid] = s;
+    for (int q = tid; q < kRedWidth; q += nt) {
+        double s = 0.0;
+        for (int i = q; i < rd.N; i += kRedWidth) s += (double)e[i];
+        part[q] = s;
+    }
     __syncthreads();
-    for (int off = nt >> 1; off > 0; off >>= 1) {
-        if (tid < off) part[tid] += part[tid + off];
+    for (int off = kRedWidth >> 1; off > 0; off >>= 1) {
+        for (int q = tid; q < off; q += nt) part[q] += part[q + off];
         __syncthreads();
     }
     if (tid == 0) d.U[r] = 0.5 * part[0];

@@ -29,6 +29,8 @@ struct re_ctx {
     int R = 0;
     int prec = RE_MIXED, form = RE_BATCHED, engine = RE_PERSISTENT, xmode = RE_SYNC;
     double rc = 0, skin = 0, dt = 0, gamma = 1.0;
+    int thermo = 0;       // kThermoLangevin | kThermoSVR
+    double svr_c = 1.0;   // exp(-dt / tau) of the velocity rescale
     int Nx = 1;
     uint64_t seed = 0;
     double ushift = 0, c1 = 0;
@@ -251,6 +253,10 @@ static StepArgs base_args(re_ctx* c)
     a.c1 = c->c1;
     a.ushiftd = c->ushift;
     a.seed = c->seed;
+    a.thermo = c->thermo;
+    a.do_u = 1;
+    a.do_svr = 0;
+    a.svr_c = c->svr_c;
     return a;
 }
 
@@ -371,6 +377,8 @@ static int run_lockstep(re_ctx* c, int64_t n)
     const bool plain = c->form == RE_PLAIN;
     const int R = c->R;
     StepArgs a = base_args(c);
+    // the velocity rescale ends every step at a stopped boundary
+    const bool svr = c->thermo == kThermoSVR;
     bool at_boundary = true;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t s = c->step;
@@ -398,8 +406,11 @@ static int run_lockstep(re_ctx* c, int64_t n)
         a.par = (int)((s + 1) & 1);
         a.force_all = 0;
         a.step = s + 1;
-        const bool stop = plain || xstep || last;
+        const bool stop = plain || xstep || last || svr;
         const StepMode mode = !stop ? kFused : ((xstep || last) ? kStopEnergy : kStop);
+        a.do_u = mode == kStopEnergy;
+        a.do_svr = svr;
+        const bool reduce = a.do_u || a.do_svr;
         if (plain) {
             for (int r = 0; r < R; ++r) {
                 a.r0 = r;
@@ -408,7 +419,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
                 a.tab = c->ctF;
                 a.blk_off = c->cF_start[r];
                 HIPCHK(c, launch_force(f64, mode, c->d, a, c->cF_count[r], c->stream));
-                if (mode == kStopEnergy) HIPCHK(c, launch_energy(f64, c->d, a, 1, c->stream));
+                if (reduce) HIPCHK(c, launch_energy(f64, c->d, a, 1, c->stream));
             }
         } else {
             a.r0 = 0;
@@ -423,10 +434,11 @@ static int run_lockstep(re_ctx* c, int64_t n)
                 HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
                 c->ev_used += 2;
             }
-            if (mode == kStopEnergy) HIPCHK(c, launch_energy(f64, c->d, a, R, c->stream));
+            if (reduce) HIPCHK(c, launch_energy(f64, c->d, a, R, c->stream));
         }
         if (stop) {
             at_boundary = true;
+            if (svr) c->pending_alpha = 1;
             if (xstep) {
                 HIPCHK(c, launch_exchange(c->d, R, c->next_attempt, c->seed, c->c1 * c->c1, -1, c->cfg.log_cap,
                                           s + 1, c->stream));
@@ -593,6 +605,14 @@ static int run_persistent(re_ctx* c, int64_t n)
     }
     HIPCHK(c, hipMemcpyAsync(c->d_target, tgt.data(), R * 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d_call, &cp, sizeof cp, hipMemcpyHostToDevice, c->stream));
+    if (c->pending_alpha) {
+        // a factor set outside the persistent engine (re_exchange) is applied
+        // by its first step
+        const std::vector<int32_t> ones(R, 1);
+        HIPCHK(c, hipMemcpyAsync(c->ps.apend, ones.data(), R * 4, hipMemcpyHostToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        c->pending_alpha = 0;
+    }
     const bool f64 = c->prec == RE_FP64;
     if (!c->gexec) {
         const PersistArgs pa = persist_args(c);
@@ -673,6 +693,9 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         return fail(nullptr, RE_EINVAL, "block_size must be 64, 128 or 256");
     const double gamma = o.gamma_set ? o.gamma : 1.0;
     if (!(gamma >= 0)) return fail(nullptr, RE_EINVAL, "gamma must be >= 0");
+    if (o.thermostat != RE_LANGEVIN && o.thermostat != RE_SVR) return fail(nullptr, RE_EINVAL, "bad thermostat");
+    if (!(o.svr_tau >= 0)) return fail(nullptr, RE_EINVAL, "svr_tau must be >= 0");
+    const double tau = o.svr_tau > 0 ? o.svr_tau : 0.5;
     if (o.autotune && o.form == RE_BATCHED) {
         // the engine and lanes per atom of this size class: cached, or timed
         const std::string key =
@@ -720,7 +743,10 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         const double ir6 = 1.0 / (r_c * r_c * r_c * r_c * r_c * r_c);
         c->ushift = 4.0 * (ir6 * ir6 - ir6);
     }
-    c->c1 = std::exp(-c->gamma * dt);
+    c->thermo = o.thermostat == RE_SVR ? kThermoSVR : kThermoLangevin;
+    // under the velocity rescale the integrator has no friction and no noise
+    c->c1 = c->thermo == kThermoSVR ? 1.0 : std::exp(-c->gamma * dt);
+    c->svr_c = std::exp(-dt / tau);
 
     // launch configuration
     c->cfg.block = o.block_size ? o.block_size : 256;
@@ -1028,6 +1054,16 @@ int re_get_state(re_ctx* c, int r, double* x, double* v)
     const RepDev& rd = c->rep[r];
     const int N = rd.N;
     int rc;
+    // velocities at the boundary include a factor still pending for the next
+    // step (exchange rescale, thermostat rescale)
+    double fac = 1.0;
+    {
+        int32_t ap = 0;
+        if (c->ps.apend && (rc = d2h(c, &ap, c->ps.apend + r, 1))) return rc;
+        if (c->pending_alpha || ap) {
+            if ((rc = d2h(c, &fac, c->d.alpha + r, 1))) return rc;
+        }
+    }
     if (c->prec == RE_MIXED) {
         std::vector<int4> p(N);
         std::vector<float4> w(N);
@@ -1042,9 +1078,9 @@ int re_get_state(re_ctx* c, int r, double* x, double* v)
                 x[3 * i + 2] = (double)p[k].z * rd.s;
             }
             if (v) {
-                v[3 * i] = w[k].x;
-                v[3 * i + 1] = w[k].y;
-                v[3 * i + 2] = w[k].z;
+                v[3 * i] = fac * w[k].x;
+                v[3 * i + 1] = fac * w[k].y;
+                v[3 * i + 2] = fac * w[k].z;
             }
         }
     } else {
@@ -1060,9 +1096,9 @@ int re_get_state(re_ctx* c, int r, double* x, double* v)
                 x[3 * i + 2] = p[k].z;
             }
             if (v) {
-                v[3 * i] = w[k].x;
-                v[3 * i + 1] = w[k].y;
-                v[3 * i + 2] = w[k].z;
+                v[3 * i] = fac * w[k].x;
+                v[3 * i + 1] = fac * w[k].y;
+                v[3 * i + 2] = fac * w[k].z;
             }
         }
     }

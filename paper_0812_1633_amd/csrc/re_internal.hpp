@@ -20,6 +20,9 @@ constexpr uint32_t kPurposeInitVel = 0u;           // Philox counter word 3 ("pu
 constexpr uint32_t kPurposeOStep = 1u;
 constexpr uint32_t kPurposeExchange = 2u;
 constexpr uint32_t kPurposeVacancy = 3u;
+constexpr uint32_t kPurposeSVR = 4u;
+constexpr int kThermoLangevin = 0;                 // BAOAB Langevin
+constexpr int kThermoSVR = 1;                      // velocity Verlet + stochastic velocity rescale
 
 // Per-replica constants, in device memory (one record per replica).
 // "pair units": the mixed form measures pair vectors in grid units of the
@@ -128,6 +131,10 @@ struct StepArgs {
     double c1;        // exp(-gamma dt)
     double ushiftd;   // u_LJ(r_c)
     uint64_t seed;    // Philox key
+    int thermo;       // kThermoLangevin | kThermoSVR
+    int do_u;         // replica reduction: potential energy
+    int do_svr;       // replica reduction: velocity rescale factor
+    double svr_c;     // exp(-dt / tau)
 };
 
 // ---- launch wrappers (re_kernels.hip) -------------------------------------

@@ -66,13 +66,16 @@ __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
     force_atom<P, MODE, TPA>(d, sa, rd, r, ia, (int)(threadIdx.x % TPA), ia < rd.N, sa.cur, sa.step, sa.par);
 }
 
+// Per-replica reductions at a stopped boundary: the potential energy
+// (do_u) and the velocity rescale factor of the thermostat (do_svr).
 template <class P>
 __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
 {
-    __shared__ double part[256];
+    __shared__ double part[512];
     const int r = sa.r0 + blockIdx.x;
     const RepDev rd = d.rep[r];
-    energy_replica<P>(d, rd, r, part);
+    if (sa.do_u) energy_replica<P>(d, rd, r, part);
+    if (sa.do_svr) svr_replica<P>(d, rd, r, sa.cur, sa.step, sa.seed, sa.svr_c, part);
 }
 
 // ---------------------------------------------------------------------------

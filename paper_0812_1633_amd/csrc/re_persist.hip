@@ -248,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     __shared__ int cnt[kMaxCells + 1];  // reorder counts; list-build tables between reorders
     static_assert(1024 * list_lds_words<kListLanes>() <= kMaxCells + 1, "list tables exceed the LDS array");
     __shared__ int part[1024];
-    __shared__ double dpart[1024];
+    __shared__ double dpart[2 * kRedWidth];
     __shared__ int sh[4];
     const PersistState& ps = pa.st;
     const CallParams& cp = *pa.call;
@@ -291,7 +291,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 
     // plan for the force phase that ends at boundary sn (leader only)
     auto plan = [&](int64_t sn) -> int {
-        int c = 0;
+        // the velocity rescale needs every step to end at a stopped boundary
+        int c = pa.sa.thermo == kThermoSVR ? kCtlStop : 0;
         if (cp.mode == kModeSync) {
             if (sn % pa.Nx == 0) c |= kCtlStop | kCtlJoin;
             if (sn >= target) c |= kCtlStop;
@@ -446,6 +447,10 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 if (leader) {
                     energy_replica<P>(d, rd, r, dpart);
                     Ucur = d.U[r];
+                    if (pa.sa.thermo == kThermoSVR) {
+                        svr_replica<P>(d, rd, r, cur, s, pa.sa.seed, pa.sa.svr_c, dpart);
+                        if (tid == 0) ps.apend[r] = 1;
+                    }
                 }
                 PT_MARK(6);
                 join_pending = (ctl & kCtlJoin) != 0;

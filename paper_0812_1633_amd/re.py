@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libre_hip.so")
 
 RE_OK, RE_EINVAL, RE_ENOMEM, RE_EDEVICE, RE_ETIMEOUT, RE_ESTATE, RE_EOVERFLOW = 0, -1, -2, -3, -4, -5, -6
-RE_LANGEVIN = 0
+RE_LANGEVIN, RE_SVR = 0, 1
 RE_MIXED, RE_FP64 = 0, 1
 RE_BATCHED, RE_PLAIN = 0, 1
 RE_LOCKSTEP, RE_PERSISTENT = 0, 1
@@ -39,7 +39,7 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("watchdog_seconds", C.c_double),
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
                 ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
-                ("team_barrier", C.c_int)]
+                ("team_barrier", C.c_int), ("svr_tau", C.c_double)]
 
 
 class XLogRec(C.Structure):
@@ -119,12 +119,14 @@ class Engine:
     N: atoms per replica (sequence of R ints); T_ladder: ascending ladder.
     precision: "mixed" | "fp64"; form: "batched" | "plain";
     engine: "persistent" | "lockstep"; exchange: "sync" | "async".
+    thermostat: "langevin" (friction gamma) | "svr" (stochastic velocity
+    rescaling, relaxation time svr_tau; 0 = 0.5).
     """
 
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
-                 tune_cache=None, autotune=False, team_barrier="auto"):
+                 tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -150,6 +152,8 @@ class Engine:
         o.tune_cache = tune_cache.encode() if tune_cache else None
         o.autotune = 1 if autotune else 0
         o.team_barrier = {"auto": RE_BARRIER_AUTO, "agent": RE_BARRIER_AGENT}[team_barrier]
+        o.thermostat = {"langevin": RE_LANGEVIN, "svr": RE_SVR}[thermostat]
+        o.svr_tau = float(svr_tau)
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))

@@ -243,3 +243,31 @@ def test_watchdog_timeout_is_reported(relib):
     e.step(20)
     assert list(e.query_steps()[0]) == [20] * R
     e.close()
+
+
+@pytest.mark.parametrize("thermostat", ["langevin", "svr"])
+def test_explicit_exchange_between_calls(relib, thermostat):
+    """re_exchange() between two re_step calls: its velocity factors are
+    applied by the next step in both engines (bit-identical runs), and
+    get_state reports the rescaled velocities right after the exchange."""
+    R, N = 4, 600
+    T = np.array([1.0, 1.001, 1.002, 1.003])  # nearly equal: swaps are accepted
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 10**6, 6, precision="fp64", engine=eng,
+                         thermostat=thermostat, watchdog_seconds=5)
+        e.step(15)
+        before = [e.get_state(r)[1] for r in range(R)]
+        slots0 = e.query_slots().copy()
+        e.exchange()
+        slots1 = e.query_slots()
+        assert not np.array_equal(slots0, slots1)
+        for r in range(R):
+            fac = np.sqrt(T[slots1[r]] / T[slots0[r]])
+            assert np.allclose(e.get_state(r)[1], fac * before[r], rtol=1e-14, atol=0), r
+        e.step(20)
+        out[eng] = [e.get_state(r) for r in range(R)]
+        e.close()
+    for r in range(R):
+        assert np.array_equal(out["lockstep"][r][0], out["persistent"][r][0]), r
+        assert np.array_equal(out["lockstep"][r][1], out["persistent"][r][1]), r
