@@ -141,8 +141,10 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
  * Advance the run (Implementation section).  RE_SYNC: every replica advances
  * exactly n steps, with an exchange attempt whenever the common step count
  * reaches a multiple of N_x.  RE_ASYNC: returns once every replica has done
- * at least n more steps; attempts are triggered by the rotating master; a
- * replica that is paired waits for its partner.  n >= 0.
+ * at least n more steps; a replica that reaches n keeps stepping (and
+ * exchanging) until the last one does, so no replica idles and the step
+ * counts differ; attempts are triggered by the rotating master; a replica
+ * that is paired waits for its partner.  n >= 0.
  * Errors: RE_EINVAL (n < 0), RE_ETIMEOUT (a device-side wait exceeded the
  * watchdog bound; the run stops at a consistent step boundary), RE_EOVERFLOW,
  * RE_EDEVICE.
@@ -168,6 +170,10 @@ int re_query_acceptance(re_ctx* ctx, int64_t* attempts, int64_t* accepts);
 
 /* Steps done and neighbour-list updates per replica (R values each). */
 int re_query_steps(re_ctx* ctx, int64_t* steps, int64_t* rebuilds);
+
+/* Exchange attempts made so far (the global attempt index of the next
+ * attempt), counting attempts that pair no replica. */
+int re_query_attempt_count(re_ctx* ctx, int64_t* n);
 
 /* Box side of each replica (R values). */
 int re_query_box(re_ctx* ctx, double* L);

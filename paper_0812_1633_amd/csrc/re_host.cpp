@@ -885,6 +885,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(c->ps.xdone, 1);
     ALLOC(c->ps.trig, 1);
     ALLOC(c->ps.parked, 1);
+    ALLOC(c->ps.reach, 1);
     ALLOC(c->ps.beat, 1);
     ALLOC(c->ps.abort, 1);
     ALLOC(c->ps.err, 1);
@@ -1024,6 +1025,13 @@ int re_query_box(re_ctx* c, double* L)
 {
     if (!c || !L) return fail(c, RE_EINVAL, "NULL argument");
     for (int r = 0; r < c->R; ++r) L[r] = c->L[r];
+    return RE_OK;
+}
+
+int re_query_attempt_count(re_ctx* c, int64_t* n)
+{
+    if (!c || !n) return fail(c, RE_EINVAL, "NULL argument");
+    *n = c->next_attempt;
     return RE_OK;
 }
 

@@ -287,6 +287,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     int64_t target = cp.mode == kModeSchedule ? 0 : cp.target[r];
     bool join_pending = false;
     bool parked = false;
+    bool reached = false;  // asynchronous mode: this replica reached its target
     double Ucur = d.U[r];
 
     // plan for the force phase that ends at boundary sn (leader only)
@@ -304,7 +305,11 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             if (!master &&
                 __hip_atomic_load(ps.trig, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (uint64_t)knext)
                 c |= kCtlStop | kCtlJoin;
-            if (sn >= target) c |= kCtlStop;
+            // stop on reaching the target, and once every replica has
+            // reached its own (then this one parks)
+            if (!reached && sn >= target) c |= kCtlStop;
+            if (reached && __hip_atomic_load(ps.reach, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)R)
+                c |= kCtlStop;
         }
         return c;
     };
@@ -325,12 +330,26 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             int c = 0;
             if (ok) {
                 bool done;
-                if (cp.mode == kModeSync)
+                if (cp.mode == kModeSync) {
                     done = s >= target;
-                else if (cp.mode == kModeSchedule)
+                } else if (cp.mode == kModeSchedule) {
                     done = asched >= cp.A;
-                else
-                    done = s >= target;
+                } else {
+                    // asynchronous: a replica past its target keeps stepping
+                    // (and exchanging) until every replica has reached its
+                    // own, so that no replica idles while others catch up
+                    if (!reached && s >= target) {
+                        reached = true;
+                        if (tid == 0)
+                            __hip_atomic_fetch_add(ps.reach, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    }
+                    if (tid == 0)
+                        sh[2] = reached && __hip_atomic_load(ps.reach, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)R;
+                    __syncthreads();
+                    done = sh[2] != 0;
+                    __syncthreads();
+                }
                 if (done && cp.mode == kModeAsync) {
                     // parked: take part in attempts triggered by others until
                     // every replica is parked and no attempt is in flight
@@ -491,6 +510,7 @@ __global__ void k_persist_prepare(DevState d, PersistArgs pa, int nteams)
         *ps.xdone = 0ull;
         *ps.trig = (uint64_t)cp.k0;
         *ps.parked = 0u;
+        *ps.reach = 0u;
         *ps.abort = 0u;
         *ps.err = 0u;
         *ps.beat = 0ull;

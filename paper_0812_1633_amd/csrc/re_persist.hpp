@@ -21,7 +21,8 @@ struct PersistState {
     int32_t* ctl;       // 2 x R: leader -> team control words (per call)
     uint64_t* xdone;    // resolutions in this call (reset per call)
     uint64_t* trig;     // next attempt to be triggered (asynchronous mode)
-    uint32_t* parked;   // replicas that reached their target (per call)
+    uint32_t* parked;   // replicas parked at the end of the call (per call)
+    uint32_t* reach;    // asynchronous mode: replicas that reached their target (per call)
     uint64_t* beat;     // progress heartbeat: force phases completed
     uint32_t* abort;    // nonzero: every team leaves
     uint32_t* err;      // kErr* bits

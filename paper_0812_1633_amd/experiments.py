@@ -1,0 +1,219 @@
+"""The Example section's measurements, on one GPU through the library.
+
+* ``efficiency``: parallel efficiency lambda against the number of replicas
+  (Scalability subsection, Fig. 1b): the total number of steps all replicas
+  do per unit of wall-clock time with exchanges, divided by the same number
+  without exchanges; synchronous exchanges with N_x = 5 against
+  asynchronous ones with N_x = 1.
+* ``diffusion``: diffusion coefficient D of log T against the observed
+  exchange stride <N_x> (Diffusion subsection, Fig. 1a), for both forms at
+  N_r = 48.
+
+The workload is the paper's Lennard-Jones liquid: 4000 atoms per replica at
+density 0.844, cutoff 2.5, neighbour list to 3.0 (skin 0.5) updated at half
+the skin, time step 0.005, stochastic velocity rescaling, and temperatures
+T_k = 0.7 * 1.0275^k.  <N_x> is the average number of steps a replica does
+between two attempts (total steps of all replicas / (replicas x attempts)).
+
+Command line: ``python -m paper_0812_1633_amd.experiments efficiency|diffusion
+[--out FILE] [...]`` prints (and writes) one JSON document.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+PAPER = dict(N=4000, rho=0.844, rc=2.5, skin=0.5, dt=0.005, Tmin=0.7, ratio=1.0275, thermostat="svr")
+
+
+def paper_ladder(Nr, Tmin=PAPER["Tmin"], ratio=PAPER["ratio"]):
+    """T_k = Tmin ratio^k, k = 0 .. Nr - 1 (Example section)."""
+    return Tmin * ratio ** np.arange(Nr, dtype=np.float64)
+
+
+def _engine(R, Nr, exchange, Nx, seed, N, **kw):
+    return R.Engine([N] * Nr, paper_ladder(Nr), PAPER["rho"], PAPER["rc"], PAPER["skin"], PAPER["dt"], Nx, seed,
+                    engine="persistent", exchange=exchange, thermostat=PAPER["thermostat"], watchdog_seconds=30,
+                    **kw)
+
+
+def _window(e, n0):
+    """Exchange records written since the log held n0 records."""
+    log, n1 = e.query_exchange_log()
+    k = n1 - n0
+    if k > len(log):
+        raise RuntimeError("exchange log ring too small for the window")
+    return log[len(log) - k:] if k > 0 else []
+
+
+def timed_run(R, Nr, exchange, Nx, steps, warmup, seed=1, N=PAPER["N"], **kw):
+    """Run `warmup` then `steps` steps; returns steps/s over all replicas,
+    atom-steps/s, <N_x> in the timed window and the attempts there."""
+    e = _engine(R, Nr, exchange, Nx, seed, N, log_capacity=1 << 20, **kw)
+    try:
+        e.step(warmup)
+        s0, _ = e.query_steps()
+        a0 = e.query_attempt_count()
+        t0 = time.perf_counter()
+        e.step(steps)
+        e.query_energies()
+        t1 = time.perf_counter()
+        s1, _ = e.query_steps()
+        att = e.query_attempt_count() - a0
+        done = int((s1 - s0).sum())
+        return dict(steps_per_s=done / (t1 - t0), atom_steps_per_s=done * N / (t1 - t0),
+                    mean_Nx=(done / (Nr * att)) if att else None, attempts=att, seconds=t1 - t0,
+                    steps_done=done)
+    finally:
+        e.close()
+
+
+def efficiency(Nr_list=(2, 4, 8, 16, 32, 48, 64, 96, 128), steps=500, warmup=100, sync_Nx=5, async_Nx=(1, 3),
+               N=PAPER["N"], seed=1):
+    """lambda(N_r): steps/s of all replicas with exchanges divided by the
+    same without exchanges, where every replica steps freely for the whole
+    call (asynchronous form with no attempt: the paper's count of steps in a
+    fixed wall-clock time).  Synchronous form at sync_Nx; asynchronous form
+    at each of async_Nx (N_x = 1 is the paper's choice; a larger N_x brings
+    <N_x> near the synchronous stride on one GPU, where a trigger reaches
+    the other replicas within one step).  The ladder reaches
+    0.7 * 1.0275^(N_r - 1): 22 at N_r = 128, too hot for dt = 0.005 much
+    beyond that."""
+    from . import re as R
+    rows = []
+    for Nr in Nr_list:
+        base = timed_run(R, Nr, "async", 10**9, steps, warmup, seed, N)
+        row = dict(Nr=int(Nr), base_steps_per_s=base["steps_per_s"])
+        runs = [("sync", sync_Nx)] + [("async", nx) for nx in async_Nx]
+        for mode, nx in runs:
+            t = timed_run(R, Nr, mode, nx, steps, warmup, seed, N)
+            row["%s_Nx%d" % (mode, nx)] = dict(mode=mode, Nx=nx, lam=t["steps_per_s"] / base["steps_per_s"],
+                                               mean_Nx=t["mean_Nx"], attempts=t["attempts"])
+        rows.append(row)
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return dict(experiment="efficiency", workload=dict(PAPER, N=N), steps=steps, warmup=warmup, rows=rows)
+
+
+# ---------------------------------------------------------------------------
+# Diffusion in log-temperature space
+
+def logT_paths(log, T_ladder, slot0, t0):
+    """Per replica, the (step, log T) points where its temperature changes:
+    replica r holds slot0[r] from its step t0[r]; an accepted swap in the
+    exchange records moves the two replicas to each other's slots at their
+    join steps."""
+    slot = np.array(slot0, dtype=np.int64)
+    lt = np.log(np.asarray(T_ladder, np.float64))
+    paths = [[(int(t0[r]), lt[slot[r]])] for r in range(len(slot))]
+    for g in sorted(log, key=lambda g: (g.attempt, g.slot_lo)):
+        if g.accepted:
+            a, b = g.rep_a, g.rep_b
+            slot[a], slot[b] = slot[b], slot[a]
+            paths[a].append((int(g.step_a), lt[slot[a]]))
+            paths[b].append((int(g.step_b), lt[slot[b]]))
+    return paths
+
+
+def _sample(path, t):
+    """log T of a step-function path at steps t (the value set at the last
+    change at or before t)."""
+    s = np.array([p[0] for p in path])
+    v = np.array([p[1] for p in path])
+    return v[np.searchsorted(s, t, side="right") - 1]
+
+
+def msd(paths, t_start, t_end, lags):
+    """Mean squared displacement of log T at the given lags (steps),
+    averaged over replicas r and over origins t in [t_start[r], t_end[r] - lag]
+    (each replica on its own step count)."""
+    out = []
+    for lag in lags:
+        acc, n = 0.0, 0
+        for r, p in enumerate(paths):
+            t = np.arange(int(t_start[r]), int(t_end[r]) - lag + 1, max(1, lag // 4))
+            if t.size == 0:
+                continue
+            d = _sample(p, t + lag) - _sample(p, t)
+            acc += float((d * d).sum())
+            n += d.size
+        out.append(acc / max(n, 1))
+    return np.array(out)
+
+
+def diffusion_coefficient(paths, t_start, t_end, dt, stride, nlags=6):
+    """D of log T per unit of time: half the least-squares slope of the MSD
+    over lags of 2, 4, ..., 2 nlags exchange strides (short enough to stay
+    well below the saturation set by the ladder width), divided by dt.
+    Returns (D, lags, msd)."""
+    lags = np.array([max(1, int(round(2 * k * stride))) for k in range(1, nlags + 1)])
+    m = msd(paths, t_start, t_end, lags)
+    A = np.vstack([lags, np.ones_like(lags)]).T.astype(np.float64)
+    slope, _ = np.linalg.lstsq(A, m, rcond=None)[0]
+    return 0.5 * slope / dt, lags, m
+
+
+def diffusion(Nr=48, sync_Nx=(2, 5, 10, 20, 50), async_Nx=(1, 2, 5, 10, 20), steps=20000, warmup=1000,
+              N=PAPER["N"], seed=1):
+    """D(<N_x>) for both forms at N_r replicas."""
+    from . import re as R
+    rows = []
+    for mode, nxs in (("sync", sync_Nx), ("async", async_Nx)):
+        for Nx in nxs:
+            e = _engine(R, Nr, mode, Nx, seed, N, log_capacity=1 << 22)
+            try:
+                e.step(warmup)
+                s0, _ = e.query_steps()
+                slot0 = e.query_slots().copy()
+                _, n0 = e.query_exchange_log(0)
+                a0 = e.query_attempt_count()
+                t0 = time.perf_counter()
+                e.step(steps)
+                t1 = time.perf_counter()
+                s1, _ = e.query_steps()
+                win = _window(e, n0)
+                paths = logT_paths(win, paper_ladder(Nr), slot0, s0)
+                att = e.query_attempt_count() - a0
+                mean_Nx = float((s1 - s0).sum()) / (Nr * max(att, 1))
+                D, lags, m = diffusion_coefficient(paths, s0, s1, PAPER["dt"], mean_Nx)
+                rows.append(dict(mode=mode, Nx=int(Nx), mean_Nx=mean_Nx, D=D, attempts=att,
+                                 accept=float(np.mean([g.accepted for g in win])) if win else None,
+                                 msd=[float(x) for x in m], lags=[int(x) for x in lags], seconds=t1 - t0))
+                print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+            finally:
+                e.close()
+    return dict(experiment="diffusion", workload=dict(PAPER, N=N), Nr=Nr, steps=steps, warmup=warmup, rows=rows)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("which", choices=["efficiency", "diffusion"])
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=None)
+    ap.add_argument("--atoms", type=int, default=PAPER["N"])
+    ap.add_argument("--replicas", type=str, default=None, help="comma-separated N_r values (efficiency)")
+    args = ap.parse_args(argv)
+    kw = dict(N=args.atoms)
+    if args.steps:
+        kw["steps"] = args.steps
+    if args.warmup is not None:
+        kw["warmup"] = args.warmup
+    if args.which == "efficiency":
+        if args.replicas:
+            kw["Nr_list"] = tuple(int(x) for x in args.replicas.split(","))
+        res = efficiency(**kw)
+    else:
+        res = diffusion(**kw)
+    txt = json.dumps(res, indent=1)
+    print(txt)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(txt + "\n")
+
+
+if __name__ == "__main__":
+    main()

@@ -70,6 +70,7 @@ def lib():
             getattr(L, f).argtypes = [vp, vp]
         L.re_query_acceptance.argtypes = [vp, vp, vp]
         L.re_query_steps.argtypes = [vp, vp, vp]
+        L.re_query_attempt_count.argtypes = [vp, C.POINTER(i64)]
         L.re_query_exchange_log.argtypes = [vp, vp, i64, C.POINTER(i64), C.POINTER(i64)]
         L.re_get_state.argtypes = [vp, C.c_int, vp, vp]
         L.re_set_state.argtypes = [vp, C.c_int, vp, vp]
@@ -89,7 +90,7 @@ def lib():
                   "re_query_slots", "re_query_box", "re_query_acceptance", "re_query_steps",
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
-                  "re_profile", "re_query_kernel_time", "re_query_config"):
+                  "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -224,6 +225,12 @@ class Engine:
         r = np.zeros(self.R, np.int64)
         _check(lib().re_query_steps(self._ctx, _ptr(s), _ptr(r)), self._ctx)
         return s, r
+
+    def query_attempt_count(self):
+        """Exchange attempts made so far (the next attempt's index)."""
+        n = C.c_int64()
+        _check(lib().re_query_attempt_count(self._ctx, C.byref(n)), self._ctx)
+        return n.value
 
     def query_exchange_log(self, cap=1 << 20):
         buf = (XLogRec * max(1, cap))()
