@@ -101,22 +101,28 @@ typedef struct {
                                     write-back; RE_BARRIER_AGENT always uses
                                     agent-scope release and acquire          */
     double svr_tau;              /* RE_SVR relaxation time (LJ units); 0: 0.5     */
+    int exchange_max_distance;   /* non-nearest-neighbour exchanges (Implementation
+                                    section): attempt k pairs ladder slots
+                                    (j, j+d), d = 1 + (w mod D) from Philox
+                                    counter (k, 0, purpose 5), j >= o = (k mod 2) d
+                                    with floor((j - o)/d) even; D = 0 or 1: the
+                                    alternating nearest-neighbour pattern    */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */
 typedef struct {
-    int64_t attempt;  /* global attempt index k (pairs slots j, j+1 with j = k mod 2) */
+    int64_t attempt;  /* global attempt index k (pairs slots j, j+d; d = 1: j = k mod 2) */
     int32_t master;   /* replica that triggered the attempt (async) or -1 (sync)  */
     int32_t slot_lo;  /* lower ladder slot j of the pair                          */
     int32_t rep_a;    /* replica that held slot j                                 */
-    int32_t rep_b;    /* replica that held slot j + 1                             */
+    int32_t rep_b;    /* replica that held slot slot_hi                           */
     int64_t step_a;   /* step count of rep_a when it joined the attempt           */
     int64_t step_b;   /* step count of rep_b when it joined the attempt           */
     double U_a, U_b;  /* potential energies at those steps (FP64)                 */
-    double T_a, T_b;  /* ladder temperatures T_j, T_{j+1}                         */
+    double T_a, T_b;  /* ladder temperatures T_j, T_{slot_hi}                     */
     double u;         /* uniform of the lower replica id (53-bit Philox)          */
     int32_t accepted; /* 1 if the temperatures were swapped                       */
-    int32_t pad_;
+    int32_t slot_hi;  /* upper ladder slot j + d of the pair                      */
 } re_xlog_rec;
 
 /*
@@ -165,7 +171,8 @@ int re_query_temps(re_ctx* ctx, double* T);
 /* Ladder slot currently held by each replica (R values). */
 int re_query_slots(re_ctx* ctx, int32_t* slot);
 
-/* Attempts and acceptances per ladder pair (k, k+1): R-1 values each. */
+/* Attempts and acceptances per ladder pair by its lower slot j (pairs
+ * (j, j+1), or (j, j+d) with non-nearest-neighbour exchanges): R-1 values each. */
 int re_query_acceptance(re_ctx* ctx, int64_t* attempts, int64_t* accepts);
 
 /* Steps done and neighbour-list updates per replica (R values each). */
@@ -211,12 +218,13 @@ int re_set_schedule(re_ctx* ctx, const int64_t* join, int64_t A);
 
 /* The device exchange rule on given inputs, for testing: replica r holds
  * slot[r] (a permutation of 0..R-1) and energy U[r]; T is the ladder.
- * Runs attempt number `attempt` of the alternating pattern on the GPU and
- * writes decisions[j] for each ladder pair (j, j+1) (0 or 1; pairs not in
- * this attempt's pattern get 255).  Needs no context.
+ * Runs attempt number `attempt` of the pattern with the given largest
+ * distance (1: alternating nearest neighbours) on the GPU and writes
+ * decisions[j] for each pair by its lower slot j (0 or 1; R-1 entries, slots
+ * that are not the lower slot of a pair get 255).  Needs no context.
  * Errors: RE_EINVAL, RE_EDEVICE. */
 int re_test_exchange(const double* U, const double* T, const int32_t* slot, int R,
-                     uint64_t seed, int64_t attempt, uint8_t* decisions);
+                     uint64_t seed, int64_t attempt, int max_distance, uint8_t* decisions);
 
 /* Device random numbers, for testing (no context needed).
  * re_test_philox: n Philox4x32-10 blocks (Salmon et al., SC'11) of the

@@ -40,7 +40,8 @@ class XRec(C.Structure):
     _fields_ = [("attempt", C.c_int64), ("slot_lo", C.c_int32), ("rep_a", C.c_int32),
                 ("rep_b", C.c_int32), ("accepted", C.c_int32), ("step_a", C.c_int64),
                 ("step_b", C.c_int64), ("U_a", C.c_double), ("U_b", C.c_double),
-                ("T_a", C.c_double), ("T_b", C.c_double), ("u", C.c_double)]
+                ("T_a", C.c_double), ("T_b", C.c_double), ("u", C.c_double), ("slot_hi", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 def lib():
@@ -86,10 +87,12 @@ def lib():
         L.oracle_metropolis.argtypes = [C.c_double] * 5
         L.oracle_metropolis.restype = C.c_int
         L.oracle_exchange.argtypes = [C.c_int32, dp, i32p, dp, C.c_void_p, C.c_uint64, C.c_int64,
-                                      dp, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+                                      C.c_int32, dp, C.c_void_p, C.c_void_p, C.c_void_p, C.POINTER(C.c_int64)]
+        L.oracle_pattern_distance.argtypes = [C.c_uint64, C.c_int64, C.c_int32]
+        L.oracle_pattern_distance.restype = C.c_int
         L.oracle_exchange.restype = C.c_int
         L.oracle_run.argtypes = [C.c_int32, i32p, i64p, dp, dp, C.c_double, C.c_double, C.c_double,
-                                 C.c_double, C.c_int, C.c_double, C.c_uint64, C.c_int, dp, dp, dp,
+                                 C.c_double, C.c_int, C.c_double, C.c_int32, C.c_uint64, C.c_int, dp, dp, dp,
                                  dp, i64p, dp, i64p,
                                  i32p, C.c_int64, C.c_int32, C.c_void_p, C.c_int64, C.c_int64,
                                  i64p, i64p, C.c_void_p, C.POINTER(C.c_int64)]
@@ -229,9 +232,15 @@ def md(rep: Replica, nsteps, skin, dt, gamma, T, seed, replica_id, use_list=True
     return rep
 
 
-def exchange(Tl, slot, U, seed, k, steps=None):
-    """One exchange attempt k over the ladder (Implementation section).
-    Returns (new slot, alpha per replica, list of XRec)."""
+def pattern_distance(seed, k, max_distance):
+    """Pairing distance of attempt k (1 for the nearest-neighbour pattern)."""
+    return lib().oracle_pattern_distance(seed, int(k), int(max_distance))
+
+
+def exchange(Tl, slot, U, seed, k, steps=None, max_distance=1):
+    """One exchange attempt k over the ladder (Implementation section):
+    ladder pairs at the attempt's distance (1: alternating nearest
+    neighbours).  Returns (new slot, alpha per replica, list of XRec)."""
     R = len(slot)
     Tl = np.ascontiguousarray(Tl, np.float64)
     slot = np.ascontiguousarray(slot, np.int32).copy()
@@ -240,7 +249,8 @@ def exchange(Tl, slot, U, seed, k, steps=None):
     recs = (XRec * max(1, R))()
     n = C.c_int64(0)
     st = None if steps is None else np.ascontiguousarray(steps, np.int64)
-    lib().oracle_exchange(R, Tl, slot, U, None if st is None else st.ctypes.data, seed, int(k), alpha,
+    lib().oracle_exchange(R, Tl, slot, U, None if st is None else st.ctypes.data, seed, int(k),
+                          int(max_distance), alpha,
                           None, None, C.cast(recs, C.c_void_p), C.byref(n))
     return slot, alpha, [recs[i] for i in range(n.value)]
 
@@ -250,7 +260,7 @@ class Ensemble:
     (each replica's atoms in atom-id order)."""
 
     def __init__(self, N, L, Tl, rc, skin, dt, gamma, seed, x=None, v=None, use_list=True,
-                 thermostat="langevin", tau=SVR_TAU):
+                 thermostat="langevin", tau=SVR_TAU, max_distance=1):
         self.N = np.ascontiguousarray(N, np.int32)
         self.R = len(self.N)
         self.off = np.zeros(self.R, np.int64)
@@ -261,6 +271,7 @@ class Ensemble:
         self.seed = int(seed)
         self.use_list = int(use_list)
         self.thermostat, self.tau = THERMOSTATS[thermostat], float(tau)
+        self.max_distance = int(max_distance)
         self.slot = np.arange(self.R, dtype=np.int32)
         tot = int(3 * self.N.astype(np.int64).sum())
         if x is None:
@@ -300,7 +311,7 @@ class Ensemble:
         recs = (XRec * max(1, cap))()
         n = C.c_int64(0)
         rc = lib().oracle_run(self.R, self.N, self.off, self.L, self.Tl, self.rc, self.skin,
-                              self.dt, self.gamma, self.thermostat, self.tau, self.seed,
+                              self.dt, self.gamma, self.thermostat, self.tau, self.max_distance, self.seed,
                               self.use_list, self.x, self.v,
                               self.F, self.xref, self.steps, self.U, self.rebuilds, self.slot,
                               int(nsteps), int(Nx),

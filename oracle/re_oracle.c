@@ -42,6 +42,7 @@
 #define ORACLE_PURPOSE_EXCHANGE 2u
 #define ORACLE_PURPOSE_VACANCY 3u
 #define ORACLE_PURPOSE_SVR 4u
+#define ORACLE_PURPOSE_PATTERN 5u
 
 #define ORACLE_LANGEVIN 0
 #define ORACLE_SVR 1
@@ -527,7 +528,17 @@ int oracle_md(int32_t N, double L, double rc, double skin, double dt, double gam
  * holding them, D = (1/T_j - 1/T_{j+1}) (U_a - U_b); the uniform of the
  * lower replica id decides; accept iff D >= 0 or u < exp(D) (standard
  * Metropolis rule of Sugita and Okamoto).  On acceptance the slots swap and
- * each velocity scale factor is sqrt(T_new / T_old).                         */
+ * each velocity scale factor is sqrt(T_new / T_old).
+ *
+ * Non-nearest-neighbour exchanges (Implementation section: the scheme
+ * extends to them) take the pairing distance d of attempt k at random in
+ * 1 .. max_distance: d = 1 + (w0 mod max_distance) with w0 the first word of
+ * Philox counter (k low, k high, 0, purpose 5) (d = 1 when max_distance is
+ * 1).  With o = (k mod 2) d, ladder slot j >= o is paired with j + d when
+ * floor((j - o) / d) is even and j + d < R; the rule above applies to the
+ * pair (j, j + d) with T_j, T_{j+d}.  For d = 1 this is the alternating
+ * pattern.  The pattern never depends on the replicas' state, so detailed
+ * balance holds for every d.                                                 */
 int oracle_metropolis(double Ua, double Ub, double Tj, double Tj1, double u)
 {
     double delta = (1.0 / Tj - 1.0 / Tj1) * (Ua - Ub);
@@ -539,25 +550,41 @@ typedef struct {
     int32_t slot_lo, rep_a, rep_b, accepted;
     int64_t step_a, step_b;
     double U_a, U_b, T_a, T_b, u;
+    int32_t slot_hi, pad;
 } oracle_xrec;
 
+int oracle_pattern_distance(uint64_t seed, int64_t k, int32_t max_distance)
+{
+    if (max_distance <= 1) return 1;
+    uint32_t w[4];
+    uint64_t a = (uint64_t)k;
+    draw4(seed, (uint32_t)a, (uint32_t)(a >> 32), 0u, ORACLE_PURPOSE_PATTERN, w);
+    return 1 + (int)(w[0] % (uint32_t)max_distance);
+}
+
 int oracle_exchange(int32_t R, const double* Tl, int32_t* slot, const double* U, const int64_t* steps,
-                    uint64_t seed, int64_t k, double* alpha,
+                    uint64_t seed, int64_t k, int32_t max_distance, double* alpha,
                     int64_t* attempts, int64_t* accepts, oracle_xrec* log, int64_t* nlog)
 {
     int32_t* rep = (int32_t*)malloc(sizeof(int32_t) * (size_t)R);
     if (!rep) return -2;
     for (int r = 0; r < R; ++r) rep[slot[r]] = r;
     for (int r = 0; r < R; ++r) alpha[r] = 1.0;
-    for (int j = (int)(k % 2); j + 1 < R; j += 2) {
-        int a = rep[j], b = rep[j + 1];
+    const int d = oracle_pattern_distance(seed, k, max_distance);
+    const int o = (int)(k % 2) * d;
+    for (int j = o; j + d < R; ++j) {
+        if (((j - o) / d) % 2 != 0) continue;
+        const int h = j + d;
+        int a = rep[j], b = rep[h];
         int lower = a < b ? a : b;
         double u = oracle_uniform53(seed, k, lower);
-        int acc = oracle_metropolis(U[a], U[b], Tl[j], Tl[j + 1], u);
+        int acc = oracle_metropolis(U[a], U[b], Tl[j], Tl[h], u);
         if (log) {
             oracle_xrec* rec = &log[*nlog];
             rec->attempt = k;
             rec->slot_lo = j;
+            rec->slot_hi = h;
+            rec->pad = 0;
             rec->rep_a = a;
             rec->rep_b = b;
             rec->accepted = acc;
@@ -566,17 +593,17 @@ int oracle_exchange(int32_t R, const double* Tl, int32_t* slot, const double* U,
             rec->U_a = U[a];
             rec->U_b = U[b];
             rec->T_a = Tl[j];
-            rec->T_b = Tl[j + 1];
+            rec->T_b = Tl[h];
             rec->u = u;
             *nlog += 1;
         }
         if (attempts) attempts[j] += 1;
         if (acc) {
             if (accepts) accepts[j] += 1;
-            slot[a] = j + 1;
+            slot[a] = h;
             slot[b] = j;
-            alpha[a] = sqrt(Tl[j + 1] / Tl[j]);
-            alpha[b] = sqrt(Tl[j] / Tl[j + 1]);
+            alpha[a] = sqrt(Tl[h] / Tl[j]);
+            alpha[b] = sqrt(Tl[j] / Tl[h]);
         }
     }
     free(rep);
@@ -602,7 +629,7 @@ int oracle_exchange(int32_t R, const double* Tl, int32_t* slot, const double* U,
  * multiplied by its factor.  attempts/accepts are per ladder pair (R - 1).  */
 int oracle_run(int32_t R, const int32_t* N, const int64_t* off, const double* L, const double* Tl,
                double rc, double skin, double dt, double gamma, int thermostat, double tau,
-               uint64_t seed, int use_list,
+               int32_t max_distance, uint64_t seed, int use_list,
                double* x, double* v, double* F, double* xref,
                int64_t* steps, double* U, int64_t* rebuilds, int32_t* slot,
                int64_t nsteps, int32_t Nx, const int64_t* sched, int64_t A, int64_t k0,
@@ -650,7 +677,7 @@ int oracle_run(int32_t R, const int32_t* N, const int64_t* off, const double* L,
         if (do_exchange) {
             /* synchronous attempt k happens at step (k + 1) N_x */
             int64_t k = sched ? k0 + a - 1 : (steps[0] / Nx) - 1;
-            oracle_exchange(R, Tl, slot, U, steps, seed, k, alpha, attempts, accepts, log, nlog);
+            oracle_exchange(R, Tl, slot, U, steps, seed, k, max_distance, alpha, attempts, accepts, log, nlog);
             for (int r = 0; r < R; ++r)
                 if (alpha[r] != 1.0)
                     for (int64_t i = 0; i < 3 * (int64_t)N[r]; ++i) v[off[r] + i] *= alpha[r];

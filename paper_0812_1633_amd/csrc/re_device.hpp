@@ -76,6 +76,16 @@ __device__ __forceinline__ void normals3d(uint4 w, double& z0, double& z1, doubl
     z2 = r23 * cos(two_pi * u3);
 }
 
+// Pairing distance of exchange attempt k: 1 + (w0 mod max_distance), w0 the
+// first word of Philox counter (k low, k high, 0, purpose 5); 1 when
+// max_distance is 1 (the nearest-neighbour pattern).
+__device__ __forceinline__ int pattern_distance(uint64_t seed, int64_t k, int max_distance)
+{
+    if (max_distance <= 1) return 1;
+    const uint4 w = draw(seed, (uint32_t)(uint64_t)k, (uint32_t)((uint64_t)k >> 32), 0u, kPurposePattern);
+    return 1 + (int)(w.x % (uint32_t)max_distance);
+}
+
 // 53-bit uniform of exchange attempt k for the lower replica id.
 __device__ __forceinline__ double uniform53(uint64_t seed, int64_t k, int32_t lower)
 {

@@ -30,6 +30,7 @@ struct re_ctx {
     int prec = RE_MIXED, form = RE_BATCHED, engine = RE_PERSISTENT, xmode = RE_SYNC;
     double rc = 0, skin = 0, dt = 0, gamma = 1.0;
     int thermo = 0;       // kThermoLangevin | kThermoSVR
+    int xmaxd = 1;        // largest ladder distance of an exchange pair
     double svr_c = 1.0;   // exp(-dt / tau) of the velocity rescale
     int Nx = 1;
     uint64_t seed = 0;
@@ -441,7 +442,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
             if (svr) c->pending_alpha = 1;
             if (xstep) {
                 HIPCHK(c, launch_exchange(c->d, R, c->next_attempt, c->seed, c->c1 * c->c1, -1, c->cfg.log_cap,
-                                          s + 1, c->stream));
+                                          s + 1, c->xmaxd, c->stream));
                 c->next_attempt += 1;
                 c->pending_alpha = 1;
             }
@@ -569,6 +570,7 @@ static PersistArgs persist_args(re_ctx* c)
     pa.log_cap = c->cfg.log_cap;
     pa.timeout = (uint64_t)(c->watchdog * 1e8);
     pa.bar_mode = c->bar_mode;
+    pa.xmaxd = c->xmaxd;
     return pa;
 }
 
@@ -686,6 +688,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.exchange_mode != RE_SYNC && o.exchange_mode != RE_ASYNC) return fail(nullptr, RE_EINVAL, "bad exchange_mode");
     if (o.team_barrier != RE_BARRIER_AUTO && o.team_barrier != RE_BARRIER_AGENT)
         return fail(nullptr, RE_EINVAL, "bad team_barrier");
+    if (o.exchange_max_distance < 0) return fail(nullptr, RE_EINVAL, "exchange_max_distance must be >= 0");
     if (o.threads_per_atom && o.threads_per_atom != 1 && o.threads_per_atom != 2 && o.threads_per_atom != 4 &&
         o.threads_per_atom != 8)
         return fail(nullptr, RE_EINVAL, "threads_per_atom must be 1, 2, 4 or 8");
@@ -744,6 +747,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         c->ushift = 4.0 * (ir6 * ir6 - ir6);
     }
     c->thermo = o.thermostat == RE_SVR ? kThermoSVR : kThermoLangevin;
+    c->xmaxd = o.exchange_max_distance > 0 ? o.exchange_max_distance : 1;
     // under the velocity rescale the integrator has no friction and no noise
     c->c1 = c->thermo == kThermoSVR ? 1.0 : std::exp(-c->gamma * dt);
     c->svr_c = std::exp(-dt / tau);
@@ -972,7 +976,7 @@ int re_exchange(re_ctx* c)
 {
     if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
     HIPCHK(c, launch_exchange(c->d, c->R, c->next_attempt, c->seed, c->c1 * c->c1, -1, c->cfg.log_cap, c->step,
-                              c->stream));
+                              c->xmaxd, c->stream));
     c->next_attempt += 1;
     c->pending_alpha = 1;
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1182,9 +1186,10 @@ int re_set_schedule(re_ctx* c, const int64_t* join, int64_t A)
 }
 
 int re_test_exchange(const double* U, const double* T, const int32_t* slot, int R, uint64_t seed, int64_t attempt,
-                     uint8_t* decisions)
+                     int max_distance, uint8_t* decisions)
 {
-    if (!U || !T || !slot || !decisions || R < 1 || R > 4096) return fail(nullptr, RE_EINVAL, "bad arguments");
+    if (!U || !T || !slot || !decisions || R < 1 || R > 4096 || max_distance < 1)
+        return fail(nullptr, RE_EINVAL, "bad arguments");
     std::vector<int> seen(R, 0);
     for (int r = 0; r < R; ++r) {
         if (slot[r] < 0 || slot[r] >= R || seen[slot[r]]++) return fail(nullptr, RE_EINVAL, "slot is not a permutation");
@@ -1199,7 +1204,7 @@ int re_test_exchange(const double* U, const double* T, const int32_t* slot, int 
     if (e == hipSuccess) e = hipMemcpy(dU, U, R * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(dT, T, R * 8, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(ds, slot, R * 4, hipMemcpyHostToDevice);
-    if (e == hipSuccess) e = launch_test_exchange(dU, dT, ds, R, seed, attempt, dd, nullptr);
+    if (e == hipSuccess) e = launch_test_exchange(dU, dT, ds, R, seed, attempt, max_distance, dd, nullptr);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e == hipSuccess && R > 1) e = hipMemcpy(decisions, dd, R - 1, hipMemcpyDeviceToHost);
     (void)hipFree(dU);

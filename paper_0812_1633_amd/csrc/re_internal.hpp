@@ -21,6 +21,7 @@ constexpr uint32_t kPurposeOStep = 1u;
 constexpr uint32_t kPurposeExchange = 2u;
 constexpr uint32_t kPurposeVacancy = 3u;
 constexpr uint32_t kPurposeSVR = 4u;
+constexpr uint32_t kPurposePattern = 5u;
 constexpr int kThermoLangevin = 0;                 // BAOAB Langevin
 constexpr int kThermoSVR = 1;                      // velocity Verlet + stochastic velocity rescale
 
@@ -55,7 +56,7 @@ struct XRec {
     int32_t master, slot_lo, rep_a, rep_b;
     int64_t step_a, step_b;
     double U_a, U_b, T_a, T_b, u;
-    int32_t accepted, pad_;
+    int32_t accepted, slot_hi;
 };
 
 // Device arrays of one context (all replicas concatenated).
@@ -147,11 +148,11 @@ hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, in
 hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,
-                           int64_t log_cap, int64_t step_all, hipStream_t st);
+                           int64_t log_cap, int64_t step_all, int max_distance, hipStream_t st);
 hipError_t launch_clear_flags(const DevState& d, int n, hipStream_t st);
 hipError_t launch_set_steps(const DevState& d, int R, int64_t step, hipStream_t st);
 hipError_t launch_test_exchange(const double* U, const double* Tl, int32_t* slot, int R, uint64_t seed,
-                                int64_t attempt, uint8_t* dec, hipStream_t st);
+                                int64_t attempt, int max_distance, uint8_t* dec, hipStream_t st);
 hipError_t launch_test_philox(const uint32_t* ctr, uint32_t key0, uint32_t key1, int n, uint32_t* out,
                               hipStream_t st);
 hipError_t launch_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int n, double* out, hipStream_t st);

@@ -80,15 +80,17 @@ __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
 
 // ---------------------------------------------------------------------------
 // Exchange attempt k (Implementation section): ladder slots (j, j+1) with
-// j = k mod 2 are paired; for the replicas a, b holding them
+// j = k mod 2 are paired -- or, with non-nearest-neighbour exchanges, slots
+// (j, j+d) at the attempt's distance d (j >= o = (k mod 2) d with
+// floor((j - o)/d) even); for the replicas a, b holding them
 // D = (1/T_j - 1/T_{j+1}) (U_a - U_b); the 53-bit uniform of the lower
 // replica id decides: accept iff D >= 0 or u < exp(D).  Accepted pairs swap
 // slots; each swapped replica's pending velocity factor is multiplied by
 // sqrt(T_new/T_old) and it takes the noise amplitude of its new temperature.
 __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, int R, int64_t k, uint64_t seed,
-                              double* alpha, double* c2, double c1sq, int64_t* att, int64_t* acc, XRec* log,
-                              int64_t* log_count, int64_t log_cap, const int64_t* steps, int64_t step_all,
-                              int32_t master, uint8_t* dec)
+                              int max_distance, double* alpha, double* c2, double c1sq, int64_t* att, int64_t* acc,
+                              XRec* log, int64_t* log_count, int64_t log_cap, const int64_t* steps,
+                              int64_t step_all, int32_t master, uint8_t* dec)
 {
     __shared__ int rep[4096];
     __shared__ int64_t lbase;
@@ -96,12 +98,16 @@ __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, 
     for (int r = tid; r < R; r += nt) rep[slot[r]] = r;
     if (tid == 0) lbase = log_count ? *log_count : 0;
     __syncthreads();
-    const int j0 = (int)(k & 1);
-    const int npairs = (R - j0) / 2;
+    // pairs (j, j + dk): j >= o with floor((j - o) / dk) even; the p-th
+    // such j is o + 2 dk (p / dk) + p mod dk
+    const int dk = pattern_distance(seed, k, max_distance);
+    const int o = (int)(k & 1) * dk;
+    const int span = R - dk - o;
+    const int npairs = span <= 0 ? 0 : (span / (2 * dk)) * dk + min(span % (2 * dk), dk);
     for (int p = tid; p < npairs; p += nt) {
-        const int j = j0 + 2 * p;
-        const int a = rep[j], b = rep[j + 1];
-        const double Ta = Tl[j], Tb = Tl[j + 1];
+        const int j = o + 2 * dk * (p / dk) + p % dk, h = j + dk;
+        const int a = rep[j], b = rep[h];
+        const double Ta = Tl[j], Tb = Tl[h];
         const double delta = (1.0 / Ta - 1.0 / Tb) * (U[a] - U[b]);
         const double u = uniform53(seed, k, a < b ? a : b);
         const int ok = (delta >= 0.0 || u < exp(delta)) ? 1 : 0;
@@ -123,11 +129,11 @@ __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, 
             rec.T_b = Tb;
             rec.u = u;
             rec.accepted = ok;
-            rec.pad_ = 0;
+            rec.slot_hi = h;
             log[(lbase + p) % log_cap] = rec;
         }
         if (ok) {
-            slot[a] = j + 1;
+            slot[a] = h;
             slot[b] = j;
             if (alpha) {  // factors of consecutive exchanges compose
                 alpha[a] *= sqrt(Tb / Ta);
@@ -144,19 +150,19 @@ __device__ void exchange_body(const double* U, const double* Tl, int32_t* slot, 
 }
 
 __global__ __launch_bounds__(1024) void k_exchange(DevState d, int R, int64_t k, uint64_t seed, double c1sq,
-                                                   int32_t master, int64_t log_cap, int64_t step_all)
+                                                   int32_t master, int64_t log_cap, int64_t step_all, int maxd)
 {
-    exchange_body(d.U, d.Tl, d.slot, R, k, seed, d.alpha, d.c2, c1sq, d.attempts, d.accepts, d.log, d.log_count,
-                  log_cap, d.steps, step_all, master, nullptr);
+    exchange_body(d.U, d.Tl, d.slot, R, k, seed, maxd, d.alpha, d.c2, c1sq, d.attempts, d.accepts, d.log,
+                  d.log_count, log_cap, d.steps, step_all, master, nullptr);
 }
 
 __global__ __launch_bounds__(1024) void k_test_exchange(const double* U, const double* Tl, int32_t* slot, int R,
-                                                        uint64_t seed, int64_t k, uint8_t* dec)
+                                                        uint64_t seed, int64_t k, int maxd, uint8_t* dec)
 {
     for (int j = threadIdx.x; j < R - 1; j += blockDim.x) dec[j] = 255;
     __syncthreads();
-    exchange_body(U, Tl, slot, R, k, seed, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, 1, nullptr, 0,
-                  -1, dec);
+    exchange_body(U, Tl, slot, R, k, seed, maxd, nullptr, nullptr, 0.0, nullptr, nullptr, nullptr, nullptr, 1,
+                  nullptr, 0, -1, dec);
 }
 
 __global__ void k_test_philox(const uint32_t* ctr, uint32_t k0, uint32_t k1, int n, uint32_t* out)
@@ -282,9 +288,10 @@ hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int n
 }
 
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,
-                           int64_t log_cap, int64_t step_all, hipStream_t st)
+                           int64_t log_cap, int64_t step_all, int max_distance, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_exchange, dim3(1), dim3(1024), 0, st, d, R, attempt, seed, c1sq, master, log_cap, step_all);
+    hipLaunchKernelGGL(k_exchange, dim3(1), dim3(1024), 0, st, d, R, attempt, seed, c1sq, master, log_cap, step_all,
+                       max_distance);
     return hipGetLastError();
 }
 
@@ -301,9 +308,9 @@ hipError_t launch_set_steps(const DevState& d, int R, int64_t step, hipStream_t 
 }
 
 hipError_t launch_test_exchange(const double* U, const double* Tl, int32_t* slot, int R, uint64_t seed,
-                                int64_t attempt, uint8_t* dec, hipStream_t st)
+                                int64_t attempt, int max_distance, uint8_t* dec, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_test_exchange, dim3(1), dim3(1024), 0, st, U, Tl, slot, R, seed, attempt, dec);
+    hipLaunchKernelGGL(k_test_exchange, dim3(1), dim3(1024), 0, st, U, Tl, slot, R, seed, attempt, max_distance, dec);
     return hipGetLastError();
 }
 

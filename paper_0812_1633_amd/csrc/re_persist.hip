@@ -171,10 +171,17 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
     if (!sh[0]) return false;
     const int32_t* sb = ps.slotbuf + (size_t)p * R;
     const int jme = sb[r];
-    const int off = jme - p;
+    // partner slot: (j, j + dk) pairs with j >= o, floor((j - o)/dk) even
+    const int dk = pattern_distance(pa.sa.seed, k, pa.xmaxd);
+    const int o = p * dk;
     int jp = -1;
-    if (off >= 0 && (off & 1) == 0 && jme + 1 < R) jp = jme + 1;
-    if (off >= 0 && (off & 1) == 1) jp = jme - 1;
+    if (jme >= o) {
+        if ((((jme - o) / dk) & 1) == 0) {
+            if (jme + dk < R) jp = jme + dk;
+        } else {
+            jp = jme - dk;
+        }
+    }
     if (jp >= 0)
         for (int q = threadIdx.x; q < R; q += blockDim.x)
             if (sb[q] == jp) sh[1] = q;
@@ -191,10 +198,10 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
             if (ok) {
                 const double Uq = ps.upost[(size_t)p * R + q];
                 const int64_t sq = ps.spost[(size_t)p * R + q];
-                const int jlo = jme < jp ? jme : jp;
+                const int jlo = jme < jp ? jme : jp, jhi = jme < jp ? jp : jme;
                 const int a = jme < jp ? r : q, b = jme < jp ? q : r;
                 const double Ua = jme < jp ? U : Uq, Ub = jme < jp ? Uq : U;
-                const double Ta = d.Tl[jlo], Tb = d.Tl[jlo + 1];
+                const double Ta = d.Tl[jlo], Tb = d.Tl[jhi];
                 const double delta = (1.0 / Ta - 1.0 / Tb) * (Ua - Ub);
                 const double u = uniform53(pa.sa.seed, k, a < b ? a : b);
                 const int acc = (delta >= 0.0 || u < exp(delta)) ? 1 : 0;
@@ -216,7 +223,7 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
                     rec.T_b = Tb;
                     rec.u = u;
                     rec.accepted = acc;
-                    rec.pad_ = 0;
+                    rec.slot_hi = jhi;
                     d.log[li % pa.log_cap] = rec;
                 }
                 if (acc) {

@@ -52,6 +52,7 @@ struct PersistArgs {
     double c1sq;
     int64_t log_cap;
     uint64_t timeout;         // watchdog, in 100 MHz clock ticks without progress
+    int xmaxd;                // largest ladder distance of an exchange pair (1: nearest neighbours)
     int bar_mode;             // team barrier: 0 agent-scope release + acquire; 1 for teams on one
                               // XCD: stores complete to the shared L2 + agent-scope acquire
 };

@@ -39,7 +39,7 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("watchdog_seconds", C.c_double),
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
                 ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
-                ("team_barrier", C.c_int), ("svr_tau", C.c_double)]
+                ("team_barrier", C.c_int), ("svr_tau", C.c_double), ("exchange_max_distance", C.c_int)]
 
 
 class XLogRec(C.Structure):
@@ -47,7 +47,7 @@ class XLogRec(C.Structure):
                 ("rep_a", C.c_int32), ("rep_b", C.c_int32), ("step_a", C.c_int64),
                 ("step_b", C.c_int64), ("U_a", C.c_double), ("U_b", C.c_double),
                 ("T_a", C.c_double), ("T_b", C.c_double), ("u", C.c_double),
-                ("accepted", C.c_int32), ("pad_", C.c_int32)]
+                ("accepted", C.c_int32), ("slot_hi", C.c_int32)]
 
 
 _lib = None
@@ -76,7 +76,7 @@ def lib():
         L.re_set_state.argtypes = [vp, C.c_int, vp, vp]
         L.re_compute_forces.argtypes = [vp, C.c_int, vp, vp]
         L.re_set_schedule.argtypes = [vp, vp, i64]
-        L.re_test_exchange.argtypes = [vp, vp, vp, C.c_int, u64, i64, vp]
+        L.re_test_exchange.argtypes = [vp, vp, vp, C.c_int, u64, i64, C.c_int, vp]
         L.re_test_philox.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int, vp]
         L.re_test_normals.argtypes = [C.c_int, u64, vp, C.c_int, vp]
         L.re_profile.argtypes = [vp, C.c_int]
@@ -122,12 +122,15 @@ class Engine:
     engine: "persistent" | "lockstep"; exchange: "sync" | "async".
     thermostat: "langevin" (friction gamma) | "svr" (stochastic velocity
     rescaling, relaxation time svr_tau; 0 = 0.5).
+    exchange_max_distance: largest ladder distance of an exchange pair (1:
+    alternating nearest neighbours).
     """
 
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
-                 tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0):
+                 tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0,
+                 exchange_max_distance=1):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -155,6 +158,7 @@ class Engine:
         o.team_barrier = {"auto": RE_BARRIER_AUTO, "agent": RE_BARRIER_AGENT}[team_barrier]
         o.thermostat = {"langevin": RE_LANGEVIN, "svr": RE_SVR}[thermostat]
         o.svr_tau = float(svr_tau)
+        o.exchange_max_distance = int(exchange_max_distance)
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))
@@ -286,15 +290,17 @@ class Engine:
 # --------------------------------------------------------------------------
 # context-free test hooks
 
-def re_test_exchange(U, T, slot, seed, attempt):
+def re_test_exchange(U, T, slot, seed, attempt, max_distance=1):
     """Device exchange rule on given energies/ladder/slots: decisions per
-    ladder pair (255 = pair not in this attempt's pattern)."""
+    pair by its lower slot (255 = not the lower slot of a pair in this
+    attempt's pattern)."""
     U = np.ascontiguousarray(U, np.float64)
     T = np.ascontiguousarray(T, np.float64)
     slot = np.ascontiguousarray(slot, np.int32)
     R = U.size
     dec = np.zeros(max(1, R - 1), np.uint8)
-    _check(lib().re_test_exchange(_ptr(U), _ptr(T), _ptr(slot), R, int(seed), int(attempt), _ptr(dec)))
+    _check(lib().re_test_exchange(_ptr(U), _ptr(T), _ptr(slot), R, int(seed), int(attempt),
+                                  int(max_distance), _ptr(dec)))
     return dec[: R - 1]
 
 

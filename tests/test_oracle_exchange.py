@@ -55,10 +55,12 @@ def test_pattern_and_scaling(orc):
         assert sorted(new) == list(range(R))
 
 
-def test_detailed_balance_enumeration(orc):
+@pytest.mark.parametrize("max_distance", [1, 2])
+def test_detailed_balance_enumeration(orc, max_distance):
     """Three replicas on a three-level system.  Each iteration resamples
     every replica exactly from Boltzmann at the temperature it holds, then
-    applies one exchange attempt.  The extended-ensemble distribution
+    applies one exchange attempt (nearest neighbours, or also the pair of
+    ladder ends at distance 2).  The extended-ensemble distribution
     pi(sigma, c) = prod_r exp(-E(c_r)/T_sigma(r)) / Z(T_sigma(r)) / R! is
     stationary; the post-exchange histogram must match it."""
     E = np.array([0.0, 1.0, 2.5])
@@ -75,7 +77,7 @@ def test_detailed_balance_enumeration(orc):
     n_iter = 30000
     for it in range(n_iter):
         c = np.array([rng.choice(3, p=boltz(Tl[slot[r]])) for r in range(R)])
-        slot, _, _ = orc.exchange(Tl, slot, E[c], 77, it)
+        slot, _, _ = orc.exchange(Tl, slot, E[c], 77, it, max_distance=max_distance)
         # record the configuration each replica carried into the exchange
         key = (tuple(slot), tuple(c))
         counts[key] = counts.get(key, 0) + 1
@@ -98,6 +100,34 @@ def test_detailed_balance_enumeration(orc):
     dof = big.sum()
     p = stats.chi2.sf(chi2, dof)
     assert p > 1e-4, (chi2, dof)
+
+
+@pytest.mark.parametrize("R,D", [(2, 1), (7, 1), (8, 3), (9, 4), (16, 5)])
+def test_distance_pattern(orc, R, D):
+    """Non-nearest-neighbour pattern: every ladder slot is in at most one
+    pair, pairs are the attempt's distance apart, every distance 1..D is
+    drawn, and D = 1 is the alternating nearest-neighbour pattern."""
+    Tl = 0.7 * 1.05 ** np.arange(R)
+    slot = np.arange(R, dtype=np.int32)[::-1].copy()
+    U = np.linspace(-100, -90, R)
+    seen = set()
+    for k in range(200):
+        d = orc.pattern_distance(9, k, D)
+        assert 1 <= d <= D
+        seen.add(d)
+        _, _, recs = orc.exchange(Tl, slot, U, 9, k, max_distance=D)
+        used = [r.slot_lo for r in recs] + [r.slot_hi for r in recs]
+        assert len(used) == len(set(used))
+        assert all(r.slot_hi - r.slot_lo == d for r in recs)
+        if D == 1:
+            assert [r.slot_lo for r in recs] == list(range(k % 2, R - 1, 2))
+        # a slot without a partner has none at distance d on either side
+        o = (k % 2) * d
+        for j in range(R):
+            expect_pair = (j >= o and ((j - o) // d) % 2 == 0 and j + d < R) or \
+                          (j - d >= o and ((j - d - o) // d) % 2 == 0)
+            assert (j in used) == expect_pair
+    assert seen == set(range(1, D + 1))
 
 
 def gamma_acceptance(d, T1, T2):
