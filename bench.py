@@ -24,7 +24,29 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "atom-steps/s over all replicas (batched mixed vs plain FP64) at stated tol"
-PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak
+PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FMA)
+# the same unit counts without packed FP32 (this build disables packed FP32
+# instructions): 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+PEAK_FP32_UNPACKED_TFLOPS = 78.6
+
+# HBM bytes per atom-step of the dominant kernel, from rocprofv3 --pmc
+# FETCH_SIZE and WRITE_SIZE runs of this benchmark, each scaled by what the
+# counter reads for a 256 MiB device copy (factors in the design notes), with
+# the hash of the kernel sources they were taken with: a changed kernel
+# reports traffic null until it is measured again.
+TRAFFIC = {
+    ("lj-32x4000", "persistent", 2): dict(fetch=300.4, write=98.1, src="a939309795eae7a1"),
+}
+KERNEL_SOURCES = ("re_persist.hip", "re_persist.hpp", "re_device.hpp", "re_internal.hpp", "re_kernels.hip")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_0812_1633_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def pair_counts(x, L, rc, rl):
@@ -51,6 +73,8 @@ def main():
     ap.add_argument("--workload", default="lj-32x4000")
     ap.add_argument("--engine", default=None, help="persistent | lockstep (default: autotuned)")
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--svr-steps", type=int, default=1000,
+                    help="steps of the same workload under stochastic velocity rescaling (0: skip)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -135,11 +159,21 @@ def main():
     flop_per_atom = np.mean([(27 * c + 9 * s) / n for c, s, n in counts])
     flops_launch = flop_per_atom * (atoms if engine_used == "lockstep" else done / max(1, k_n))
     achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+    atom_steps_launch = atoms if engine_used == "lockstep" else done / max(1, k_n)
+    tr = TRAFFIC.get((args.workload, engine_used, tpa_used))
+    src = kernel_source_hash()
+    traffic = None
+    if tr and tr["src"] == src:
+        traffic = (tr["fetch"] + tr["write"]) * atom_steps_launch
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": None,
-                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed>",
-                "kernel_ms": k_ms, "launches_timed": k_n,
-                "flop_per_atom_step": float(flop_per_atom)}
+                "frac": (achieved / PEAK_FP32_TFLOPS) if achieved else None, "traffic": traffic,
+                "traffic_unit": "bytes per launch (HBM, counter-measured)",
+                "hbm_GBps_at_traffic": (traffic / (k_ms * 1e-3) / 1e9) if traffic and k_ms > 0 else None,
+                "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
+                "frac_unpacked": (achieved / PEAK_FP32_UNPACKED_TFLOPS) if achieved else None,
+                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed,%d>" % tpa_used,
+                "kernel_ms": k_ms, "launches_timed": k_n, "atom_steps_per_launch": atom_steps_launch,
+                "flop_per_atom_step": float(flop_per_atom), "kernel_src": src}
     eng.close()
 
     # ---- plain per-replica FP64 form ---------------------------------------
@@ -156,6 +190,21 @@ def main():
         plain = {"value": pv, "unit": "atom-steps/s", "ms_per_step": 1e3 * (t1 - t0) / args.plain_steps,
                  "steps": args.plain_steps, "ratio_mixed_over_plain": value / pv}
         ep.close()
+
+    # ---- the paper's thermostat (stochastic velocity rescaling) ------------
+    svr = None
+    if args.svr_steps > 0:
+        es = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", thermostat="svr",
+                      engine=engine_used, threads_per_atom=tpa_used, **kw)
+        es.step(min(args.svr_steps, 100))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        es.step(args.svr_steps)
+        es.query_energies()
+        t1 = time.perf_counter()
+        svr = {"value": atoms * args.svr_steps / (t1 - t0), "unit": "atom-steps/s", "steps": args.svr_steps,
+               "ms_per_step": 1e3 * (t1 - t0) / args.svr_steps}
+        es.close()
 
     # ---- CPU baseline: the oracle on a bounded sample ----------------------
     cpu = None
@@ -184,7 +233,7 @@ def main():
                       "engine": engine_used, "threads_per_atom": tpa_used, "team_size": team_used,
                       "tuning": "explicit" if args.engine else "autotuned",
                       "parallelism": "replicas batched on 1 GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain,
+           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "thermostat_svr": svr,
            "tolerance": dict(tol, passed=bool(ok)),
            "exchange": {"attempts": int(acc_att.sum()), "accepted": int(acc_acc.sum())},
            "rebuilds_per_replica_step": float((reb1 - reb0).sum() / max(1, (steps1 - steps0).sum()))}
