@@ -231,46 +231,59 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     if (dx * dx + dy * dy + dz * dz > P::lim2(rd)) atomicOr(&d.flag[(size_t)((step + 1) & 1) * sa.R + r], 1u);
 }
 
-// Reorder one replica by cell with the whole workgroup: counting sort of the
-// atoms into the cell grid (counts in LDS), each cell then ordered by atom
-// id so the result does not depend on scheduling; x_ref := x.  The other
-// position buffer and the velocity scratch serve as gather space.
+// Reorder one replica by cell with the whole workgroup (blockDim a multiple
+// of 64, at most 4096): counting sort of the atoms into the cell grid
+// (counts in LDS), each cell then ordered by atom id so the result does not
+// depend on scheduling; x_ref := x.  The other position buffer and the
+// velocity scratch serve as gather space.  `cnt` holds kMaxCells + 1 ints of
+// LDS; when the counts and three N-int scratch arrays fit there the scratch
+// stays in LDS, otherwise it goes to the global per-atom arrays.
 template <class P>
 __device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int cur, int* cnt, int* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int nc = rd.ncell, ncc = nc * nc * nc;
+    const int nc = rd.ncell, ncc = nc * nc * nc, N = rd.N;
     typename P::pos_t* pos = P::pos(d, cur) + rd.base;
     typename P::pos_t* tmp = P::pos(d, cur ^ 1) + rd.base;
     typename P::vel_t* vel = P::vel(d) + rd.base;
     typename P::vel_t* velt = P::velt(d) + rd.base;
-    int32_t* cellid = d.cellid + rd.base;
-    int32_t* rank = d.rank + rd.base;
-    int32_t* perm = d.perm + rd.base;
+    const bool in_lds = ncc + 1 + 3 * N <= kMaxCells + 1;
+    int32_t* cellid = in_lds ? cnt + ncc + 1 : d.cellid + rd.base;
+    int32_t* rank = in_lds ? cellid + N : d.rank + rd.base;
+    int32_t* perm = in_lds ? rank + N : d.perm + rd.base;
     for (int c = tid; c < ncc; c += nt) cnt[c] = 0;
     __syncthreads();
-    for (int i = tid; i < rd.N; i += nt) {
+    for (int i = tid; i < N; i += nt) {
         const typename P::pos_t p = pos[i];
         const int c = (P::cellc(p.x, rd) * nc + P::cellc(p.y, rd)) * nc + P::cellc(p.z, rd);
         cellid[i] = c;
         rank[i] = atomicAdd(&cnt[c], 1);
     }
     __syncthreads();
-    // exclusive scan of the counts: contiguous chunks per thread, then a
-    // scan of the chunk sums
+    // exclusive scan of the counts: contiguous chunks per thread; the chunk
+    // sums are scanned within each wave by shuffles, then across the waves
     const int chunk = (ncc + nt - 1) / nt;
     const int c0 = tid * chunk, c1 = min(ncc, c0 + chunk);
     int s = 0;
     for (int c = c0; c < c1; ++c) s += cnt[c];
-    part[tid] = s;
-    __syncthreads();
-    for (int off = 1; off < nt; off <<= 1) {
-        const int v = tid >= off ? part[tid - off] : 0;
-        __syncthreads();
-        part[tid] += v;
-        __syncthreads();
+    const int lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    int x = s;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
     }
-    int run = part[tid] - s;
+    if (lane == 63) part[wv] = x;
+    __syncthreads();
+    if (wv == 0) {
+        int t = lane < nw ? part[lane] : 0;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(t, o, 64);
+            if (lane >= o) t += y;
+        }
+        if (lane < nw) part[64 + lane] = t;
+    }
+    __syncthreads();
+    int run = (wv > 0 ? part[64 + wv - 1] : 0) + x - s;
     for (int c = c0; c < c1; ++c) {
         const int n = cnt[c];
         cnt[c] = run;
@@ -286,9 +299,9 @@ __device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int 
     // order every cell by atom id: the ids in cell order go to the free
     // `cellid` scratch; each atom's place in its cell is the number of atoms
     // of the cell with a smaller id.  The ordered slots go to `rank`.
-    for (int k = tid; k < rd.N; k += nt) cellid[k] = P::id(pos[perm[k]]);
+    for (int k = tid; k < N; k += nt) cellid[k] = P::id(pos[perm[k]]);
     __syncthreads();
-    for (int k = tid; k < rd.N; k += nt) {
+    for (int k = tid; k < N; k += nt) {
         int lo = 0, hi = ncc - 1;  // the cell of sorted slot k
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;

@@ -442,10 +442,9 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
                                              cnt + tid * list_lds_words<kListLanes>());
                 }
-                if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
-                    ok = false;
-                    break;
-                }
+                // every workgroup builds the lists of its own atoms and then
+                // computes their forces: a workgroup barrier orders the two
+                __syncthreads();
                 PT_MARK(3);
             }
             const bool stop = (ctl & kCtlStop) != 0;
