@@ -12,8 +12,7 @@
  * Every function is written for obviousness, not speed: double precision,
  * plain loops, no blocking, no fusion.  Each cites the passage it follows.
  *
- * Readings of the paper where it is silent (they are listed, with reasons,
- * in the design notes of the repository):
+ * Readings of the paper where it is silent:
  *   - periodic cubic box, minimum image; side L rounded to a multiple of
  *     2^-12 so that the box and grid-aligned positions are exact in both
  *     single and double precision;

@@ -702,7 +702,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.autotune && o.form == RE_BATCHED) {
         // the engine and lanes per atom of this size class: cached, or timed
         const std::string key =
-            tune_key(R, N_atoms, o.rho_per_replica, rho, r_c, skin, o.precision, o.exchange_mode);
+            tune_key(R, N_atoms, o.rho_per_replica, rho, r_c, skin, o.precision, o.exchange_mode, o.thermostat);
         TuneChoice ch{};
         if (!tune_lookup(o.tune_cache, key, ch)) {
             const int rt = tune_run(R, N_atoms, T_ladder, rho, r_c, skin, dt, N_x, seed, o, ch);

@@ -23,11 +23,11 @@ namespace re {
 static std::mutex g_mu;
 static std::map<std::string, TuneChoice> g_mem;
 
-// Size class: device, precision, exchange mode, replica count, the median
+// Size class: device, precision, exchange mode, thermostat, replica count, the median
 // and the spread of the atom counts (log2 bins), the mean density (0.05
 // bins), r_c and the list radius.
 std::string tune_key(int R, const int32_t* N, const double* rho_r, double rho, double rc, double skin, int prec,
-                     int xmode)
+                     int xmode, int thermo)
 {
     std::vector<int32_t> n(N, N + R);
     std::sort(n.begin(), n.end());
@@ -44,7 +44,7 @@ std::string tune_key(int R, const int32_t* N, const double* rho_r, double rho, d
             if (*p == ':') *p = '+';
     }
     char buf[256];
-    std::snprintf(buf, sizeof buf, "%s|p%d|x%d|R%d|N%d|S%d|rho%.2f|rc%.3f|rl%.3f", arch, prec, xmode, R,
+    std::snprintf(buf, sizeof buf, "%s|p%d|x%d|t%d|R%d|N%d|S%d|rho%.2f|rc%.3f|rl%.3f", arch, prec, xmode, thermo, R,
                   (int)std::lround(std::log2((double)med) * 2.0),
                   (int)std::lround(std::log2((double)n[R - 1] / (double)n[0])), std::round(rs * 20.0) / 20.0, rc,
                   rc + skin);

@@ -14,7 +14,7 @@ struct TuneChoice {
 };
 
 std::string tune_key(int R, const int32_t* N, const double* rho_r, double rho, double rc, double skin, int prec,
-                     int xmode);
+                     int xmode, int thermo);
 bool tune_lookup(const char* path, const std::string& key, TuneChoice& out);
 void tune_store(const char* path, const std::string& key, const TuneChoice& c);
 int tune_run(int R, const int32_t* N, const double* T, double rho, double rc, double skin, double dt, int Nx,

@@ -3,10 +3,12 @@ of the Example section; Bussi, Donadio and Parrinello 2007): velocity Verlet
 steps with the rescale at every step boundary, through the C-ABI.
 
 * 100 steps from the same injected state: positions and kinetic energy of
-  the oracle (FP64 1e-9, mixed 1e-4), both batched engines, over two calls;
+  the oracle (FP64 1e-9, mixed 1e-4), both batched engines and the plain
+  per-replica form, over two calls;
 * lockstep and persistent engines give bit-identical runs with exchanges;
 * a synchronous FP64 run makes the oracle's exchange decisions;
-* the kinetic energy on the GPU has the canonical mean and variance.
+* the kinetic energy on the GPU has the canonical mean and variance;
+* an asynchronous run keeps the rule and the replicas' temperatures.
 """
 import numpy as np
 import pytest
@@ -41,13 +43,14 @@ def mi_dist(a, b, L):
     return np.abs(d).max()
 
 
-@pytest.mark.parametrize("engine", ["lockstep", "persistent"])
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("engine,precision", [("lockstep", "fp64"), ("lockstep", "mixed"), ("persistent", "fp64"),
+                                              ("persistent", "mixed"), ("plain", "fp64")])
 def test_svr_trajectory_matches_oracle(relib, engine, precision):
     R, N, seed = 3, 500, 11
     T = W.ladder(0.8, 1.6, R)
-    eng = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 1000, seed, precision=precision, engine=engine,
-                       thermostat="svr", watchdog_seconds=5)
+    form = "plain" if engine == "plain" else "batched"
+    eng = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 1000, seed, precision=precision, form=form,
+                       engine="lockstep" if engine == "plain" else engine, thermostat="svr", watchdog_seconds=5)
     states = []
     for r in range(R):
         L, x, v = melted(N, 0.8442, 60 + r, T[r])
@@ -137,4 +140,29 @@ def test_svr_canonical_kinetic_energy(relib):
         k = np.array(Ks[r])
         assert k.mean() == pytest.approx(0.5 * Nf * T[r], rel=0.012), r
         assert k.var() == pytest.approx(0.5 * Nf * T[r] ** 2, rel=0.3), r
+    e.close()
+
+
+def test_svr_async_run(relib):
+    """Asynchronous exchanges under the velocity rescale: every replica does
+    at least n steps, every logged decision follows the rule with the Philox
+    uniform of the lower replica id, and the kinetic temperatures stay near
+    the temperatures the replicas hold."""
+    R, N, Nx, n, seed = 6, 500, 3, 600, 23
+    T = W.ladder(0.8, 1.3, R)
+    e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, seed, exchange="async", thermostat="svr",
+                     svr_tau=0.1, watchdog_seconds=10)
+    e.step(n)
+    steps, _ = e.query_steps()
+    assert steps.min() >= n
+    log, total = e.query_exchange_log()
+    assert total > 20
+    for g in log:
+        assert oracle.metropolis(g.U_a, g.U_b, g.T_a, g.T_b, g.u) == g.accepted
+        assert g.u == oracle.uniform53(seed, g.attempt, min(g.rep_a, g.rep_b))
+    Tr = e.query_temps()
+    for r in range(R):
+        _, v = e.get_state(r)
+        Tk = (v * v).sum() / (3 * N - 3)
+        assert abs(Tk - Tr[r]) / Tr[r] < 0.15, (r, Tk, Tr[r])
     e.close()
