@@ -672,6 +672,22 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
             f.w = 0;
             P::frc(d)[g] = f;
             if constexpr (MODE == kStopEnergy || MODE == kRefresh) P::epot(d)[g] = e;
+            if constexpr (MODE == kStop || MODE == kStopEnergy) {
+                // the atom's terms of the velocity rescale at this boundary:
+                // v.v and its squared normals of the chi-square sum (Philox
+                // counter (atom id, step, replica, purpose 4); all three but
+                // for atom 0, whose first normal is R1, and atom 1, whose
+                // first is left out: 3N - 4 terms in all)
+                if (sa.thermo == kThermoSVR) {
+                    const int id = P::id(pi);
+                    double z0, z1, z2;
+                    normals3d(draw(sa.seed, (uint32_t)id, (uint32_t)step_next, (uint32_t)r, kPurposeSVR), z0, z1, z2);
+                    const double chi =
+                        (id == 0 ? 0.0 : (id == 1 ? 0.0 : z0 * z0)) + (id == 0 ? 0.0 : z1 * z1 + z2 * z2);
+                    d.svrq[g] = make_double2((double)vx * (double)vx + (double)vy * (double)vy + (double)vz * (double)vz,
+                                             chi);
+                }
+            }
         }
     }
 }
@@ -687,29 +703,25 @@ constexpr int kRedWidth = 256;
 
 // Stochastic velocity rescale of replica r at step boundary s (Example
 // section: the thermostat; Bussi, Donadio and Parrinello 2007), run by one
-// workgroup (part: 2 kRedWidth doubles): K = sum v^2 / 2 and the chi-square sum S of N_f - 1 = 3N - 4
-// squared normals (Philox counter (atom id, s, r, purpose 4): all three
-// normals of every atom but the first normal of atom 0, which is R1, its
-// other two and the first of atom 1), both in FP64; then
+// workgroup (part: 2 kRedWidth doubles) after a stopping force phase has
+// left each atom's terms in svrq: K = sum v.v / 2 and the chi-square sum S of
+// N_f - 1 = 3N - 4 squared normals, both in FP64 (fixed slice order); R1 is
+// the first normal of atom 0 (Philox counter (0, s, r, purpose 4)); then
 //   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
 // Kbar = N_f T / 2 at the replica's temperature, and the pending velocity
 // factor is multiplied by sqrt(K'/K) (K = 0: unchanged).
 template <class P>
-__device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int cur, int64_t s, uint64_t seed,
-                            double c, double* part)
+__device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
+                            double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const typename P::vel_t* v = P::vel(d) + rd.base;
-    const typename P::pos_t* x = P::pos(d, cur) + rd.base;  // for the atom ids
+    const double2* q2 = d.svrq + rd.base;
     for (int q = tid; q < kRedWidth; q += nt) {
         double k2 = 0.0, chi = 0.0;
         for (int i = q; i < rd.N; i += kRedWidth) {
-            const typename P::vel_t vi = v[i];
-            k2 += (double)vi.x * (double)vi.x + (double)vi.y * (double)vi.y + (double)vi.z * (double)vi.z;
-            const int id = P::id(x[i]);
-            double z0, z1, z2;
-            normals3d(draw(seed, (uint32_t)id, (uint32_t)s, (uint32_t)r, kPurposeSVR), z0, z1, z2);
-            chi += (id == 0 ? 0.0 : (id == 1 ? 0.0 : z0 * z0)) + (id == 0 ? 0.0 : z1 * z1 + z2 * z2);
+            const double2 t = q2[i];
+            k2 += t.x;
+            chi += t.y;
         }
         part[q] = k2;
         part[kRedWidth + q] = chi;

@@ -878,6 +878,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.log_count, 1);
     ALLOC(d.overflow, 1);
     ALLOC(d.fq, 4 * slots);
+    if (c->thermo == kThermoSVR) ALLOC(d.svrq, slots);
     ALLOC(c->ps.slotbuf, 2 * R);
     ALLOC(c->ps.post, R);
     ALLOC(c->ps.upost, 2 * R);

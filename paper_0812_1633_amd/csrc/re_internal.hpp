@@ -73,6 +73,7 @@ struct DevState {
     double4* frcd;
     double4* xrefd;
     double* epotd;
+    double2* svrq;      // velocity rescale: per atom v.v and its chi-square terms at the last stop
     double4* veltd;
     // neighbour machinery
     int32_t* perm;      // reorder scratch: new slot -> old slot

@@ -246,8 +246,9 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
 }
 
 // control word of a boundary: bit 0 stop at the next force phase, bit 1 join
-// at that boundary, bit 2 leave the run here
-constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4;
+// at that boundary, bit 2 leave the run here, bit 3 the stop needs the
+// potential energy (a stop for the velocity rescale alone does not)
+constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4, kCtlEnergy = 8;
 
 template <class P, int TPA>
 __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
@@ -299,8 +300,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 
     // plan for the force phase that ends at boundary sn (leader only)
     auto plan = [&](int64_t sn) -> int {
-        // the velocity rescale needs every step to end at a stopped boundary
-        int c = pa.sa.thermo == kThermoSVR ? kCtlStop : 0;
+        int c = 0;
         if (cp.mode == kModeSync) {
             if (sn % pa.Nx == 0) c |= kCtlStop | kCtlJoin;
             if (sn >= target) c |= kCtlStop;
@@ -318,6 +318,12 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             if (reached && __hip_atomic_load(ps.reach, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == (uint32_t)R)
                 c |= kCtlStop;
         }
+        // every stop for an exchange or the end of the call computes U (in
+        // the asynchronous form every stop: a replica may find at the
+        // boundary that it parks, and then joins attempts with its U)
+        if ((c & kCtlStop) || cp.mode == kModeAsync) c |= kCtlEnergy;
+        // the velocity rescale needs every step to end at a stopped boundary
+        if (pa.sa.thermo == kThermoSVR) c |= kCtlStop;
         return c;
     };
 
@@ -448,13 +454,16 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 PT_MARK(3);
             }
             const bool stop = (ctl & kCtlStop) != 0;
+            const bool with_u = (ctl & kCtlEnergy) != 0;
             const int apb = nt / TPA;
             for (int base = i0; base < i1; base += apb) {
                 const int ia = base + tid / TPA;
-                if (stop)
+                if (!stop)
+                    force_atom<P, kFused, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+                else if (with_u)
                     force_atom<P, kStopEnergy, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
                 else
-                    force_atom<P, kFused, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+                    force_atom<P, kStop, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
             }
             if (leader && !stop && tid == 0) ps.ctl[(size_t)((s + 2) & 1) * R + r] = plan(s + 2);
             PT_MARK(4);
@@ -470,10 +479,12 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             s += 1;
             if (stop) {
                 if (leader) {
-                    energy_replica<P>(d, rd, r, dpart);
-                    Ucur = d.U[r];
+                    if (with_u) {
+                        energy_replica<P>(d, rd, r, dpart);
+                        Ucur = d.U[r];
+                    }
                     if (pa.sa.thermo == kThermoSVR) {
-                        svr_replica<P>(d, rd, r, cur, s, pa.sa.seed, pa.sa.svr_c, dpart);
+                        svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, dpart);
                         if (tid == 0) ps.apend[r] = 1;
                     }
                 }
