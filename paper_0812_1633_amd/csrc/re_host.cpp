@@ -31,6 +31,8 @@ struct re_ctx {
     double rc = 0, skin = 0, dt = 0, gamma = 1.0;
     int thermo = 0;       // kThermoLangevin | kThermoSVR
     int xmaxd = 1;        // largest ladder distance of an exchange pair
+    bool wide_reorder = false;  // lockstep: reorder large replicas with grid-wide passes
+    int64_t total_atoms = 0;
     double svr_c = 1.0;   // exp(-dt / tau) of the velocity rescale
     int Nx = 1;
     uint64_t seed = 0;
@@ -271,8 +273,7 @@ static int refresh_replicas(re_ctx* c, int r0, int nrep)
     a.par = 0;
     for (int r = r0; r < r0 + nrep; ++r) {
         a.r0 = r;
-        HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-        HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->N[r], c->stream));
+        HIPCHK(c, launch_rebuild(f64, c->d, a, 1, c->N[r], c->wide_reorder, c->stream));
         a.tab = c->ctF;
         a.blk_off = c->cF_start[r];
         HIPCHK(c, launch_force(f64, kRefresh, c->d, a, c->cF_count[r], c->stream));
@@ -415,8 +416,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
         if (plain) {
             for (int r = 0; r < R; ++r) {
                 a.r0 = r;
-                HIPCHK(c, launch_reorder(f64, c->d, a, 1, c->stream));
-                HIPCHK(c, launch_listbuild(f64, c->d, a, 1, c->N[r], c->stream));
+                HIPCHK(c, launch_rebuild(f64, c->d, a, 1, c->N[r], c->wide_reorder, c->stream));
                 a.tab = c->ctF;
                 a.blk_off = c->cF_start[r];
                 HIPCHK(c, launch_force(f64, mode, c->d, a, c->cF_count[r], c->stream));
@@ -424,8 +424,7 @@ static int run_lockstep(re_ctx* c, int64_t n)
             }
         } else {
             a.r0 = 0;
-            HIPCHK(c, launch_reorder(f64, c->d, a, R, c->stream));
-            HIPCHK(c, launch_listbuild(f64, c->d, a, R, c->nmax, c->stream));
+            HIPCHK(c, launch_rebuild(f64, c->d, a, R, c->total_atoms, c->wide_reorder, c->stream));
             a.blk_off = 0;
             a.tab = c->btF;
             const bool timed = c->prof && mode == kFused && c->ev_used + 2 <= (int)c->ev.size();
@@ -778,6 +777,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         slots += rd.Np;
         rd.L = c->L[r];
         c->nmax = std::max(c->nmax, rd.N);
+        c->total_atoms += rd.N;
         // fine cells: side >= r_list / 2 (the list build scans 5 x 5 x 5 cells)
         int nc = (int)std::floor(rd.L / (0.5 * rlist * (1.0 + 1e-5)));
         nc = std::max(1, std::min(nc, kMaxCellsPerSide));
@@ -819,6 +819,9 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         }
     }
     c->total_slots = slots;
+    // one workgroup reorders a replica of a few thousand atoms in tens of
+    // microseconds; larger replicas are reordered by grid-wide passes
+    c->wide_reorder = c->nmax >= 16384;
     c->total_cells = cells;
 
     int rc = 0;
@@ -878,6 +881,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.log_count, 1);
     ALLOC(d.overflow, 1);
     ALLOC(d.fq, 4 * slots);
+    ALLOC(d.wtab, 4 * (size_t)R + 4);
     if (c->thermo == kThermoSVR) ALLOC(d.svrq, slots);
     ALLOC(c->ps.slotbuf, 2 * R);
     ALLOC(c->ps.post, R);

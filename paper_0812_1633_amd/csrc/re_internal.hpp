@@ -74,6 +74,7 @@ struct DevState {
     double4* xrefd;
     double* epotd;
     double2* svrq;      // velocity rescale: per atom v.v and its chi-square terms at the last stop
+    int32_t* wtab;      // work table of the replicas whose lists are rebuilt (lockstep), 4 R + 4 ints
     double4* veltd;
     // neighbour machinery
     int32_t* perm;      // reorder scratch: new slot -> old slot
@@ -144,8 +145,12 @@ struct StepArgs {
 enum StepMode { kFused = 0, kStop = 1, kStopEnergy = 2, kQuery = 3, kRefresh = 4 };
 
 hipError_t launch_start(bool fp64, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
-hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
-hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int nmax, hipStream_t st);
+// List update of the replicas [sa.r0, sa.r0 + nrep) whose update flag of
+// parity sa.par is set (all with sa.force_all): work table, reorder by cell
+// (one workgroup per replica, or grid-wide passes when `wide`), list build
+// over the rebuilt replicas' atoms only.  atoms: sum of N over the range.
+hipError_t launch_rebuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int64_t atoms, bool wide,
+                          hipStream_t st);
 hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st);
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,

@@ -4,6 +4,8 @@
 // and the test hooks.  The per-atom arithmetic lives in re_device.hpp.
 #include "re_device.hpp"
 
+#include <algorithm>
+
 namespace re {
 
 template <class P>
@@ -18,34 +20,278 @@ __global__ __launch_bounds__(256) void k_start(DevState d, StepArgs sa)
     start_atom<P>(d, sa, rd, r, i, sa.cur, sa.step, sa.apply_alpha != 0);
 }
 
-// One workgroup per replica; runs only where the update flag of this parity
-// is set (or everywhere with force_all).
-template <class P>
-__global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArgs sa)
+// ---------------------------------------------------------------------------
+// List updates.  A work table first lists the replicas whose update flag is
+// set, with prefix sums of their list-build blocks, atoms and cell entries;
+// the reorder and list kernels then run over those replicas' work only.
+
+constexpr int kListAPB = 256 / kListLanes;  // atoms per list-build block
+
+// Last k in [0, n) with pre[k] <= v (pre nondecreasing, pre[0] = 0 <= v).
+__device__ __forceinline__ int work_slot(const int32_t* pre, int n, int v)
 {
-    const int r = sa.r0 + blockIdx.x;
-    if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
-    __shared__ int cnt[kMaxCells + 1];
-    __shared__ int part[kReorderThreads];
-    const RepDev rd = d.rep[r];
-    reorder_replica<P>(d, rd, r, sa.cur, cnt, part);
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= v)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
 }
 
-// blockIdx.y = replica (from r0), 256 / kListLanes atoms per block.
-template <class P>
-__global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa)
+// Table layout (nrep replicas from sa.r0): blk[nrep+1], atm[nrep+1],
+// cel[nrep+1] prefix sums; rep[nrep] the rebuilt replicas in order; nflag.
+struct WorkTable {
+    int32_t *blk, *atm, *cel, *rep, *nflag;
+};
+__device__ __forceinline__ WorkTable work_table(const DevState& d, int nrep)
 {
-    constexpr int APB = 256 / kListLanes;  // atoms per block
+    WorkTable w;
+    w.blk = d.wtab;
+    w.atm = w.blk + nrep + 1;
+    w.cel = w.atm + nrep + 1;
+    w.rep = w.cel + nrep + 1;
+    w.nflag = w.rep + nrep;
+    return w;
+}
+
+__device__ __forceinline__ void rebuild_work(const DevState& d, const StepArgs& sa, int k, int& nb, int& na, int& nc,
+                                             int& nf)
+{
+    const int r = sa.r0 + k;
+    const bool f = sa.force_all || d.flag[(size_t)sa.par * sa.R + r] != 0;
+    const int N = d.rep[r].N, c = d.rep[r].ncell;
+    nb = f ? (N + kListAPB - 1) / kListAPB : 0;
+    na = f ? N : 0;
+    nc = f ? c * c * c + 1 : 0;
+    nf = f ? 1 : 0;
+}
+
+// One workgroup of 1024: each thread sums a chunk of replicas, a two-level
+// shuffle scan gives the chunk offsets, the chunk writes its prefixes.
+__global__ __launch_bounds__(1024) void k_rebuild_table(DevState d, StepArgs sa, int nrep)
+{
+    __shared__ int wsum[4][16];
+    __shared__ int wpre[4][16];
+    const WorkTable w = work_table(d, nrep);
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    const int chunk = (nrep + nt - 1) / nt;
+    const int k0 = min(nrep, tid * chunk), k1 = min(nrep, k0 + chunk);
+    int s[4] = {0, 0, 0, 0};
+    for (int k = k0; k < k1; ++k) {
+        int v[4];
+        rebuild_work(d, sa, k, v[0], v[1], v[2], v[3]);
+        for (int q = 0; q < 4; ++q) s[q] += v[q];
+    }
+    int x[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        x[q] = s[q];
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x[q], o, 64);
+            if (lane >= o) x[q] += y;
+        }
+        if (lane == 63) wsum[q][wv] = x[q];
+    }
+    __syncthreads();
+    if (tid < 4) {
+        int run = 0;
+        for (int u = 0; u < nw; ++u) {
+            wpre[tid][u] = run;
+            run += wsum[tid][u];
+        }
+    }
+    __syncthreads();
+    int run[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) run[q] = wpre[q][wv] + x[q] - s[q];
+    for (int k = k0; k < k1; ++k) {
+        int v[4];
+        rebuild_work(d, sa, k, v[0], v[1], v[2], v[3]);
+        w.blk[k] = run[0];
+        w.atm[k] = run[1];
+        w.cel[k] = run[2];
+        if (v[3]) w.rep[run[3]] = sa.r0 + k;
+        for (int q = 0; q < 4; ++q) run[q] += v[q];
+    }
+    if (tid == nt - 1) {
+        w.blk[nrep] = run[0];
+        w.atm[nrep] = run[1];
+        w.cel[nrep] = run[2];
+        *w.nflag = run[3];
+    }
+}
+
+// Reorder with one workgroup per rebuilt replica.
+template <class P>
+__global__ __launch_bounds__(kReorderThreads) void k_reorder(DevState d, StepArgs sa, int nrep)
+{
+    __shared__ int cnt[kMaxCells + 1];
+    __shared__ int part[kReorderThreads];
+    const WorkTable w = work_table(d, nrep);
+    for (int j = blockIdx.x; j < *w.nflag; j += gridDim.x) {
+        const int r = w.rep[j];
+        const RepDev rd = d.rep[r];
+        reorder_replica<P>(d, rd, r, sa.cur, cnt, part);
+    }
+}
+
+// Reorder with grid-wide passes over the rebuilt replicas' atoms, the same
+// result as reorder_replica: counting sort into the cell grid (counts in the
+// cell-start array), each cell ordered by atom id, positions and velocities
+// gathered into the new order, x_ref := x.
+#define RE_FOR_WORK(pre, ...)                                                                \
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < (pre)[nrep];                    \
+         g += gridDim.x * blockDim.x) {                                                      \
+        const int k = work_slot((pre), nrep, g);                                             \
+        const int r = sa.r0 + k;                                                             \
+        const RepDev rd = d.rep[r];                                                          \
+        const int i = g - (pre)[k];                                                          \
+        (void)r;                                                                             \
+        __VA_ARGS__                                                                          \
+    }
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_zero(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.cel, { d.cell_start[rd.cell_base + i] = 0; })
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_count(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, {
+        const int nc = rd.ncell;
+        const typename P::pos_t p = P::pos(d, sa.cur)[rd.base + i];
+        const int c = (P::cellc(p.x, rd) * nc + P::cellc(p.y, rd)) * nc + P::cellc(p.z, rd);
+        d.cellid[rd.base + i] = c;
+        d.rank[rd.base + i] = atomicAdd(&d.cell_start[rd.cell_base + c], 1);
+    })
+}
+
+// exclusive scan of each rebuilt replica's counts in place (one workgroup of
+// 1024 per replica); the entry past the last cell becomes N
+__global__ __launch_bounds__(1024) void k_ro_scan(DevState d, StepArgs sa, int nrep)
+{
+    __shared__ int wsum[16];
+    const WorkTable w = work_table(d, nrep);
+    const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wv = tid >> 6, nw = nt >> 6;
+    for (int j = blockIdx.x; j < *w.nflag; j += gridDim.x) {
+        const RepDev rd = d.rep[w.rep[j]];
+        const int ncc = rd.ncell * rd.ncell * rd.ncell;
+        int32_t* cs = d.cell_start + rd.cell_base;
+        const int chunk = (ncc + nt - 1) / nt;
+        const int c0 = min(ncc, tid * chunk), c1 = min(ncc, c0 + chunk);
+        int s = 0;
+        for (int c = c0; c < c1; ++c) s += cs[c];
+        int x = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(x, o, 64);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[wv] = x;
+        __syncthreads();
+        int base = 0;
+        for (int u = 0; u < wv; ++u) base += wsum[u];
+        int run = base + x - s;
+        for (int c = c0; c < c1; ++c) {
+            const int n = cs[c];
+            cs[c] = run;
+            run += n;
+        }
+        if (tid == 0) cs[ncc] = rd.N;
+        (void)nw;
+        __syncthreads();
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_scatter(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, {
+        const int32_t* cs = d.cell_start + rd.cell_base;
+        d.perm[rd.base + cs[d.cellid[rd.base + i]] + d.rank[rd.base + i]] = i;
+    })
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_ids(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, { d.cellid[rd.base + i] = P::id(P::pos(d, sa.cur)[rd.base + d.perm[rd.base + i]]); })
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_rank(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, {
+        const int ncc = rd.ncell * rd.ncell * rd.ncell;
+        const int32_t* cs = d.cell_start + rd.cell_base;
+        const int32_t* ids = d.cellid + rd.base;
+        int lo = 0, hi = ncc - 1;  // the cell of sorted slot i
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (cs[mid] <= i)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int a = cs[lo], e = cs[lo + 1];
+        const int myid = ids[i];
+        int rk = 0;
+        for (int m = a; m < e; ++m) rk += ids[m] < myid ? 1 : 0;
+        d.rank[rd.base + a + rk] = d.perm[rd.base + i];
+    })
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_gather(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, {
+        const int src = d.rank[rd.base + i];
+        P::pos(d, sa.cur ^ 1)[rd.base + i] = P::pos(d, sa.cur)[rd.base + src];
+        P::velt(d)[rd.base + i] = P::vel(d)[rd.base + src];
+    })
+}
+
+template <class P>
+__global__ __launch_bounds__(256) void k_ro_copy(DevState d, StepArgs sa, int nrep)
+{
+    const WorkTable w = work_table(d, nrep);
+    RE_FOR_WORK(w.atm, {
+        const typename P::pos_t p = P::pos(d, sa.cur ^ 1)[rd.base + i];
+        P::pos(d, sa.cur)[rd.base + i] = p;
+        P::xref(d)[rd.base + i] = p;
+        P::vel(d)[rd.base + i] = P::velt(d)[rd.base + i];
+        if (i == 0) d.rebuilds[r] += 1;
+    })
+}
+#undef RE_FOR_WORK
+
+// List build over the rebuilt replicas' atoms: block vb of the table holds
+// kListAPB atoms of one replica.
+template <class P>
+__global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa, int nrep)
+{
     constexpr int W = list_lds_words<kListLanes>();
     __shared__ int lds[256 * W];
-    const int r = sa.r0 + blockIdx.y;
-    if (!sa.force_all && d.flag[(size_t)sa.par * sa.R + r] == 0) return;
-    const RepDev rd = d.rep[r];
-    const int i = blockIdx.x * APB + (int)(threadIdx.x / kListLanes);
-    if ((int)blockIdx.x * APB >= rd.N) return;
-    const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
-    list_rows<P, kListLanes>(d, rd, pos, i, i < rd.N, (int)(threadIdx.x % kListLanes), sa.tpa, sa.M,
-                             lds + threadIdx.x * W);
+    const WorkTable w = work_table(d, nrep);
+    for (int vb = blockIdx.x; vb < w.blk[nrep]; vb += gridDim.x) {
+        const int k = work_slot(w.blk, nrep, vb);
+        const int r = sa.r0 + k;
+        const RepDev rd = d.rep[r];
+        const int i = (vb - w.blk[k]) * kListAPB + (int)(threadIdx.x / kListLanes);
+        const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
+        list_rows<P, kListLanes>(d, rd, pos, i, i < rd.N, (int)(threadIdx.x % kListLanes), sa.tpa, sa.M,
+                                 lds + threadIdx.x * W);
+    }
 }
 
 // Force + epilogue; the first block of each replica also marks the list of
@@ -223,26 +469,34 @@ hipError_t launch_start(bool fp64, const DevState& d, const StepArgs& sa, int nb
     return fp64 ? start_t<PF64>(d, sa, nblk, st) : start_t<PMixed>(d, sa, nblk, st);
 }
 
-hipError_t launch_reorder(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st)
+template <class P>
+static hipError_t rebuild_t(const DevState& d, const StepArgs& sa, int nrep, int64_t atoms, bool wide, hipStream_t st)
 {
-    if (nrep <= 0) return hipSuccess;
-    if (fp64)
-        hipLaunchKernelGGL(k_reorder<PF64>, dim3(nrep), dim3(kReorderThreads), 0, st, d, sa);
-    else
-        hipLaunchKernelGGL(k_reorder<PMixed>, dim3(nrep), dim3(kReorderThreads), 0, st, d, sa);
+    hipLaunchKernelGGL(k_rebuild_table, dim3(1), dim3(1024), 0, st, d, sa, nrep);
+    const int gatom = (int)std::min<int64_t>((atoms + 255) / 256, 4096);
+    if (wide) {
+        const int gcell = std::min(4096, nrep * (kMaxCells + 1) / 256 + 1);
+        hipLaunchKernelGGL(k_ro_zero<P>, dim3(gcell), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_count<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_scan, dim3(std::min(nrep, 1024)), dim3(1024), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_scatter<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_ids<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_rank<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_gather<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+        hipLaunchKernelGGL(k_ro_copy<P>, dim3(gatom), dim3(256), 0, st, d, sa, nrep);
+    } else {
+        hipLaunchKernelGGL(k_reorder<P>, dim3(std::min(nrep, 1024)), dim3(kReorderThreads), 0, st, d, sa, nrep);
+    }
+    const int gblk = (int)std::min<int64_t>(atoms / kListAPB + nrep, 8192);
+    hipLaunchKernelGGL(k_listrows<P>, dim3(gblk), dim3(256), 0, st, d, sa, nrep);
     return hipGetLastError();
 }
 
-hipError_t launch_listbuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int nmax, hipStream_t st)
+hipError_t launch_rebuild(bool fp64, const DevState& d, const StepArgs& sa, int nrep, int64_t atoms, bool wide,
+                          hipStream_t st)
 {
     if (nrep <= 0) return hipSuccess;
-    const int apb = 256 / kListLanes;
-    const dim3 grid((nmax + apb - 1) / apb, nrep);
-    if (fp64)
-        hipLaunchKernelGGL(k_listrows<PF64>, grid, dim3(256), 0, st, d, sa);
-    else
-        hipLaunchKernelGGL(k_listrows<PMixed>, grid, dim3(256), 0, st, d, sa);
-    return hipGetLastError();
+    return fp64 ? rebuild_t<PF64>(d, sa, nrep, atoms, wide, st) : rebuild_t<PMixed>(d, sa, nrep, atoms, wide, st);
 }
 
 template <class P, int MODE>

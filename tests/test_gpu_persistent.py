@@ -271,3 +271,22 @@ def test_explicit_exchange_between_calls(relib, thermostat):
     for r in range(R):
         assert np.array_equal(out["lockstep"][r][0], out["persistent"][r][0]), r
         assert np.array_equal(out["lockstep"][r][1], out["persistent"][r][1]), r
+
+
+def test_wide_reorder_equals_persistent(relib):
+    """Replicas of 20000 atoms are reordered by grid-wide passes in the
+    lockstep engine and by one workgroup in the persistent engine: the same
+    canonical order, so the runs agree bitwise (with exchanges)."""
+    R, N, Nx = 3, 20000, 15
+    T = W.ladder(0.8, 1.2, R)
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 8, engine=eng, watchdog_seconds=10)
+        e.step(45)
+        out[eng] = ([e.get_state(r) for r in range(R)], e.query_steps()[1].copy(), e.query_slots().copy())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert np.array_equal(a[1], b[1]) and a[1].min() >= 2
+    assert np.array_equal(a[2], b[2])
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
