@@ -231,37 +231,13 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     if (dx * dx + dy * dy + dz * dz > P::lim2(rd)) atomicOr(&d.flag[(size_t)((step + 1) & 1) * sa.R + r], 1u);
 }
 
-// Reorder one replica by cell with the whole workgroup (blockDim a multiple
-// of 64, at most 4096): counting sort of the atoms into the cell grid
-// (counts in LDS), each cell then ordered by atom id so the result does not
-// depend on scheduling; x_ref := x.  The other position buffer and the
-// velocity scratch serve as gather space.  `cnt` holds kMaxCells + 1 ints of
-// LDS; when the counts and three N-int scratch arrays fit there the scratch
-// stays in LDS, otherwise it goes to the global per-atom arrays.
-template <class P>
-__device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int cur, int* cnt, int* part)
+// Exclusive scan of the ncc cell counts in LDS with the whole workgroup, in
+// place; cnt[ncc] := N.  Contiguous chunks per thread; the chunk sums are
+// scanned within each wave by shuffles, then across the waves (`part`: 128
+// ints of LDS).  Ends with a workgroup barrier.
+__device__ __forceinline__ void cell_scan(int* cnt, int ncc, int N, int* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const int nc = rd.ncell, ncc = nc * nc * nc, N = rd.N;
-    typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-    typename P::pos_t* tmp = P::pos(d, cur ^ 1) + rd.base;
-    typename P::vel_t* vel = P::vel(d) + rd.base;
-    typename P::vel_t* velt = P::velt(d) + rd.base;
-    const bool in_lds = ncc + 1 + 3 * N <= kMaxCells + 1;
-    int32_t* cellid = in_lds ? cnt + ncc + 1 : d.cellid + rd.base;
-    int32_t* rank = in_lds ? cellid + N : d.rank + rd.base;
-    int32_t* perm = in_lds ? rank + N : d.perm + rd.base;
-    for (int c = tid; c < ncc; c += nt) cnt[c] = 0;
-    __syncthreads();
-    for (int i = tid; i < N; i += nt) {
-        const typename P::pos_t p = pos[i];
-        const int c = (P::cellc(p.x, rd) * nc + P::cellc(p.y, rd)) * nc + P::cellc(p.z, rd);
-        cellid[i] = c;
-        rank[i] = atomicAdd(&cnt[c], 1);
-    }
-    __syncthreads();
-    // exclusive scan of the counts: contiguous chunks per thread; the chunk
-    // sums are scanned within each wave by shuffles, then across the waves
     const int chunk = (ncc + nt - 1) / nt;
     const int c0 = tid * chunk, c1 = min(ncc, c0 + chunk);
     int s = 0;
@@ -289,9 +265,105 @@ __device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int 
         cnt[c] = run;
         run += n;
     }
+    if (tid == 0) cnt[ncc] = N;
     __syncthreads();
-    if (tid == 0) cnt[ncc] = rd.N;
+}
+
+// Reorder with every atom held in registers (at most K per thread): one
+// read of x and v, the arrival order in each cell from LDS atomics, the ids
+// of each cell's atoms in LDS, and each atom's place in its cell the number
+// of atoms of the cell with a smaller id; x, x_ref and v are then written in
+// place at the new slots.
+template <class P, int K>
+__device__ void reorder_in_registers(const DevState& d, const RepDev& rd, int r, int cur, int* cnt, int* part)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nc = rd.ncell, ncc = nc * nc * nc, N = rd.N;
+    typename P::pos_t* pos = P::pos(d, cur) + rd.base;
+    typename P::vel_t* vel = P::vel(d) + rd.base;
+    int* idk = cnt + ncc + 1;  // ids in (cell, arrival) order
+    for (int c = tid; c < ncc; c += nt) cnt[c] = 0;
     __syncthreads();
+    typename P::pos_t px[K];
+    typename P::vel_t pv[K];
+    int cc[K], ar[K];
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        const int i = tid + j * nt;
+        if (i < N) {
+            px[j] = pos[i];
+            pv[j] = vel[i];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        cc[j] = 0;
+        ar[j] = 0;
+        if (tid + j * nt < N) {
+            cc[j] = (P::cellc(px[j].x, rd) * nc + P::cellc(px[j].y, rd)) * nc + P::cellc(px[j].z, rd);
+            ar[j] = atomicAdd(&cnt[cc[j]], 1);
+        }
+    }
+    __syncthreads();
+    cell_scan(cnt, ncc, N, part);
+#pragma unroll
+    for (int j = 0; j < K; ++j)
+        if (tid + j * nt < N) idk[cnt[cc[j]] + ar[j]] = P::id(px[j]);
+    __syncthreads();
+    int32_t* cstart = d.cell_start + rd.cell_base;
+    for (int c = tid; c <= ncc; c += nt) cstart[c] = cnt[c];
+    typename P::pos_t* xref = P::xref(d) + rd.base;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+        if (tid + j * nt < N) {
+            const int a = cnt[cc[j]], e = cnt[cc[j] + 1];
+            const int myid = P::id(px[j]);
+            int rk = 0;
+            for (int m = a; m < e; ++m) rk += idk[m] < myid ? 1 : 0;
+            pos[a + rk] = px[j];
+            xref[a + rk] = px[j];
+            vel[a + rk] = pv[j];
+        }
+    }
+    if (tid == 0) d.rebuilds[r] += 1;
+    __syncthreads();
+}
+
+// Reorder one replica by cell with the whole workgroup (blockDim a multiple
+// of 64, at most 4096): counting sort of the atoms into the cell grid
+// (counts in LDS), each cell then ordered by atom id so the result does not
+// depend on scheduling; x_ref := x.  The other position buffer and the
+// velocity scratch serve as gather space.  `cnt` holds kMaxCells + 1 ints of
+// LDS; when the counts and three N-int scratch arrays fit there the scratch
+// stays in LDS, otherwise it goes to the global per-atom arrays.
+template <class P>
+__device__ void reorder_replica(const DevState& d, const RepDev& rd, int r, int cur, int* cnt, int* part)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    const int nc = rd.ncell, ncc = nc * nc * nc, N = rd.N;
+    constexpr int K = P::kF64 ? 2 : 4;
+    if (N <= K * nt && ncc + 1 + N <= kMaxCells + 1) {
+        reorder_in_registers<P, K>(d, rd, r, cur, cnt, part);
+        return;
+    }
+    typename P::pos_t* pos = P::pos(d, cur) + rd.base;
+    typename P::pos_t* tmp = P::pos(d, cur ^ 1) + rd.base;
+    typename P::vel_t* vel = P::vel(d) + rd.base;
+    typename P::vel_t* velt = P::velt(d) + rd.base;
+    const bool in_lds = ncc + 1 + 3 * N <= kMaxCells + 1;
+    int32_t* cellid = in_lds ? cnt + ncc + 1 : d.cellid + rd.base;
+    int32_t* rank = in_lds ? cellid + N : d.rank + rd.base;
+    int32_t* perm = in_lds ? rank + N : d.perm + rd.base;
+    for (int c = tid; c < ncc; c += nt) cnt[c] = 0;
+    __syncthreads();
+    for (int i = tid; i < N; i += nt) {
+        const typename P::pos_t p = pos[i];
+        const int c = (P::cellc(p.x, rd) * nc + P::cellc(p.y, rd)) * nc + P::cellc(p.z, rd);
+        cellid[i] = c;
+        rank[i] = atomicAdd(&cnt[c], 1);
+    }
+    __syncthreads();
+    cell_scan(cnt, ncc, N, part);
     int32_t* cstart = d.cell_start + rd.cell_base;
     for (int c = tid; c <= ncc; c += nt) cstart[c] = cnt[c];
     for (int i = tid; i < rd.N; i += nt) perm[cnt[cellid[i]] + rank[i]] = i;
@@ -383,15 +455,16 @@ __host__ __device__ constexpr int list_lds_words()
 // kept as a bit mask; a scan of the lane counts over the group places them,
 // so the list holds lane 0's hits, then lane 1's, ..., each in scan order.
 // Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa]
-// (tpa a power of two).  `lds`: list_lds_words<LPA>() words of this lane.
+// (tpa a power of two).  `pos` and `cs` (the replica's positions and cell
+// starts) may be global arrays or copies in LDS.  `lds`: list_lds_words<LPA>()
+// words of this lane.
 template <class P, int LPA>
-__device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos, int i,
-                                          bool act, int q, int tpa, int M, int* lds)
+__device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos,
+                                          const int32_t* cs, int i, bool act, int q, int tpa, int M, int* lds)
 {
     using real = typename P::real;
     constexpr int RPL = ListRowSets<LPA>::kRPL;
     const int nc = rd.ncell;
-    const int32_t* cs = d.cell_start + rd.cell_base;
     const typename P::pos_t pi = pos[act ? i : 0];
     // this lane's ranges: flat start lds[2 n], slot offset lds[2 n + 1]
     int T = 0, nr = 0;
@@ -450,43 +523,51 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
     }
     lds[2 * nr] = T;
     const real rl2 = P::rl2(rd);
-    // flat candidate k -> slot
-    auto slot = [&](int k) {
-        const int ri = __popcll(bounds & ((2ull << k) - 1ull));
-        return k + lds[2 * ri + 1];
-    };
     auto test = [&](const typename P::pos_t& pj, int j) {
         real dx, dy, dz;
         P::diff(pi, pj, rd, dx, dy, dz);
         // bitwise, so that no load is moved under a branch
         return (dx * dx + dy * dy + dz * dz < rl2) & (j != i);
     };
+    // positions by 32-bit byte offsets from the replica's base
+    const char* pbase = reinterpret_cast<const char*>(pos);
+    auto load = [&](uint32_t j) {
+        return *reinterpret_cast<const typename P::pos_t*>(pbase + j * (uint32_t)sizeof(typename P::pos_t));
+    };
     const int T64 = T < 64 ? T : 64;
     uint64_t mk = 0;
     int cnt = 0;
+    int ri = 0;  // ranges started at flat indices 1..k0
     for (int k0 = 0; k0 < T64; k0 += 4) {
+        // the range of candidates k0 .. k0 + 3 from the range-start bits
+        // above k0; the slot of flat candidate k is k plus its range's offset
+        // (a candidate past the lane's end reads at most three slots past the
+        // last range, inside the position arrays' slack, and is masked out)
+        const uint32_t w = (uint32_t)(bounds >> (k0 + 1));
+        int rr[4];
+        rr[0] = ri;
+        rr[1] = rr[0] + (int)(w & 1u);
+        rr[2] = rr[1] + (int)((w >> 1) & 1u);
+        rr[3] = rr[2] + (int)((w >> 2) & 1u);
+        ri = rr[3] + (int)((w >> 3) & 1u);
+        uint32_t jj[4];
         typename P::pos_t pj[4];
-        int jj[4];
-        // without branches: a candidate past the end reads an in-range slot
-        // and is masked out of the test
 #pragma unroll
-        for (int u = 0; u < 4; ++u) jj[u] = min(max(slot(k0 + u), 0), rd.N - 1);
+        for (int u = 0; u < 4; ++u) jj[u] = (uint32_t)(k0 + u + lds[2 * rr[u] + 1]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) pj[u] = pos[jj[u]];
+        for (int u = 0; u < 4; ++u) pj[u] = load(jj[u]);
+        uint32_t nib = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int k = k0 + u;
-            const bool hit = (k < T64) & test(pj[u], jj[u]);
-            mk |= hit ? (1ull << k) : 0ull;
-            cnt += hit ? 1 : 0;
-        }
+        for (int u = 0; u < 4; ++u) nib |= ((k0 + u < T64) & test(pj[u], (int)jj[u])) ? (1u << u) : 0u;
+        mk |= (uint64_t)nib << k0;
+        cnt += __popc(nib);
     }
     // candidates past the mask (only with very full rows): walk the ranges
     auto walk = [&](auto&& on_hit) {
         for (int n = 0; n < nr; ++n) {
             const int k1 = lds[2 * n + 2], off = lds[2 * n + 1];
             for (int k = max(lds[2 * n], 64); k < k1; ++k)
-                if (test(pos[k + off], k + off)) on_hit(k + off);
+                if (test(load((uint32_t)(k + off)), k + off)) on_hit(k + off);
         }
     };
     if (T > 64) walk([&](int) { ++cnt; });
@@ -499,17 +580,29 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
     }
     const int tot = __shfl(incl, LPA - 1, LPA);
     int o = incl - cnt;
+    // entry o of atom i: word ((o / tpa) Np + i) tpa + o % tpa of the list
     uint32_t* nl = d.nl + rd.nl_base;
-    const size_t Np = (size_t)rd.Np;
-    const int lg = __ffs(tpa) - 1;
+    const uint32_t jump = (uint32_t)rd.Np * (uint32_t)tpa - (uint32_t)(tpa - 1);
+    uint32_t e = (uint32_t)(o / tpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
+                 (uint32_t)(o & (tpa - 1));
     auto put = [&](int j) {
-        if (o < M) nl[((size_t)(o >> lg) * Np + i) * tpa + (o & (tpa - 1))] = (uint32_t)j;
+        if (o < M) nl[e] = (uint32_t)j;
         ++o;
+        e += (o & (tpa - 1)) ? 1u : jump;
     };
-    while (mk) {
-        const int k = __builtin_ctzll(mk);
-        mk &= mk - 1;
-        put(slot(k));
+    // hits in flat order; the range of hit k from the range starts at 1..k
+    uint32_t mlo = (uint32_t)mk, mhi = (uint32_t)(mk >> 32);
+    const uint32_t blo = (uint32_t)bounds, bhi = (uint32_t)(bounds >> 32);
+    while (mlo) {
+        const int k = __builtin_ctz(mlo);
+        mlo &= mlo - 1u;
+        put(k + lds[2 * __popc(blo & ((2u << k) - 1u)) + 1]);
+    }
+    const int rhi = __popc(blo);
+    while (mhi) {
+        const int k = __builtin_ctz(mhi);
+        mhi &= mhi - 1u;
+        put(32 + k + lds[2 * (rhi + __popc(bhi & ((2u << k) - 1u))) + 1]);
     }
     if (T > 64) walk(put);
     if (act && q == 0) {

@@ -791,6 +791,12 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         c->cells_max = std::max(c->cells_max, nc * nc * nc);
         rd.nl_base = nl;
         nl += (int64_t)rd.Np * c->cfg.M;
+        // list words of one replica are addressed with 32-bit offsets
+        if ((int64_t)rd.Np * c->cfg.M >= ((int64_t)1 << 31)) {
+            delete c;
+            return fail(nullptr, RE_EINVAL, "replica %d: %lld list entries exceed 2^31", r,
+                        (long long)rd.Np * c->cfg.M);
+        }
         if (c->prec == RE_MIXED) {
             rd.s = rd.L * 0x1p-32;
             rd.inv_s = 0x1p32 / rd.L;
@@ -844,16 +850,16 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
 #define ALLOC(p, n) \
     if ((rc = dalloc(c, &(p), (n))) != 0) return bail(rc);
     if (c->prec == RE_MIXED) {
-        ALLOC(d.posi[0], slots);
-        ALLOC(d.posi[1], slots);
+        ALLOC(d.posi[0], slots + kPosSlack);
+        ALLOC(d.posi[1], slots + kPosSlack);
         ALLOC(d.velf, slots);
         ALLOC(d.frcf, slots);
         ALLOC(d.xrefi, slots);
         ALLOC(d.epotf, slots);
         ALLOC(d.veltf, slots);
     } else {
-        ALLOC(d.posd[0], slots);
-        ALLOC(d.posd[1], slots);
+        ALLOC(d.posd[0], slots + kPosSlack);
+        ALLOC(d.posd[1], slots + kPosSlack);
         ALLOC(d.veld, slots);
         ALLOC(d.frcd, slots);
         ALLOC(d.xrefd, slots);

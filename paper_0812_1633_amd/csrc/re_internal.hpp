@@ -10,10 +10,12 @@ namespace re {
 constexpr int kMaxCellsPerSide = 32;               // cell grid cap (cells may exceed r_list/2)
 constexpr int kMaxCells = kMaxCellsPerSide * kMaxCellsPerSide * kMaxCellsPerSide;
 constexpr int kReorderThreads = 1024;              // one workgroup per replica
+constexpr int kPersistLdsWords = 36864;            // persistent kernel's shared int array (144 KiB)
 #ifndef RE_LIST_LANES
 #define RE_LIST_LANES 8
 #endif
 constexpr int kListLanes = RE_LIST_LANES;          // list-build lanes per atom (4 or 8)
+constexpr int kPosSlack = 64;                      // position slots past the last replica (list-build reads)
 constexpr int kListSlackRows = 8;                  // list rows read past a replica's block by the
                                                    // force loop's prefetch (values unused)
 constexpr uint32_t kPurposeInitVel = 0u;           // Philox counter word 3 ("purpose")

@@ -253,8 +253,11 @@ constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4, kCtlEnergy = 8;
 template <class P, int TPA>
 __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 {
-    __shared__ int cnt[kMaxCells + 1];  // reorder counts; list-build tables between reorders
-    static_assert(1024 * list_lds_words<kListLanes>() <= kMaxCells + 1, "list tables exceed the LDS array");
+    // reorder counts; between reorders the list-build tables, then (when
+    // they fit) copies of the replica's positions and cell starts
+    __shared__ int cnt[kPersistLdsWords];
+    constexpr int kTabWords = 1024 * list_lds_words<kListLanes>();
+    static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
     __shared__ double dpart[2 * kRedWidth];
     __shared__ int sh[4];
@@ -443,10 +446,27 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 }
                 PT_MARK(2);
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-                for (int base = i0; base < i1; base += nt / kListLanes) {
-                    const int i = base + tid / kListLanes;
-                    list_rows<P, kListLanes>(d, rd, pos, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
-                                             cnt + tid * list_lds_words<kListLanes>());
+                const int32_t* cs = d.cell_start + rd.cell_base;
+                constexpr int kPosWords = (int)(sizeof(typename P::pos_t) / sizeof(int));
+                const int ncs = rd.ncell * rd.ncell * rd.ncell + 1;
+                if (kTabWords + kPosWords * rd.N + ncs <= kPersistLdsWords) {
+                    // the candidates' positions and the cell starts from LDS
+                    typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
+                    int32_t* lcs = cnt + kTabWords + kPosWords * rd.N;
+                    for (int k = tid; k < rd.N; k += nt) lpos[k] = pos[k];
+                    for (int k = tid; k < ncs; k += nt) lcs[k] = cs[k];
+                    __syncthreads();
+                    for (int base = i0; base < i1; base += nt / kListLanes) {
+                        const int i = base + tid / kListLanes;
+                        list_rows<P, kListLanes>(d, rd, lpos, lcs, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
+                                                 cnt + tid * list_lds_words<kListLanes>());
+                    }
+                } else {
+                    for (int base = i0; base < i1; base += nt / kListLanes) {
+                        const int i = base + tid / kListLanes;
+                        list_rows<P, kListLanes>(d, rd, pos, cs, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
+                                                 cnt + tid * list_lds_words<kListLanes>());
+                    }
                 }
                 // every workgroup builds the lists of its own atoms and then
                 // computes their forces: a workgroup barrier orders the two
