@@ -455,7 +455,8 @@ __host__ __device__ constexpr int list_lds_words()
 // kept as a bit mask; a scan of the lane counts over the group places them,
 // so the list holds lane 0's hits, then lane 1's, ..., each in scan order.
 // Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa]
-// (tpa a power of two).  `pos` and `cs` (the replica's positions and cell
+// (tpa a power of two) and holds the byte offset of the neighbour's position
+// from the replica's first slot.  `pos` and `cs` (the replica's positions and cell
 // starts) may be global arrays or copies in LDS.  `lds`: list_lds_words<LPA>()
 // words of this lane.
 template <class P, int LPA>
@@ -586,7 +587,7 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
     uint32_t e = (uint32_t)(o / tpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
                  (uint32_t)(o & (tpa - 1));
     auto put = [&](int j) {
-        if (o < M) nl[e] = (uint32_t)j;
+        if (o < M) nl[e] = (uint32_t)j * (uint32_t)sizeof(typename P::pos_t);
         ++o;
         e += (o & (tpa - 1)) ? 1u : jump;
     };
@@ -612,37 +613,44 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
 }
 
 // LJ force (+ energy) on atom slot ia over its Verlet list, TPA lanes per
-// atom (lane q takes entries q, q + TPA, ...), then the step epilogue
-// selected by MODE:
-//   kFused:      v += h F (ends this step), v += h F, x += h v, O, x += h v
-//                (the next step's first half; positions to the other buffer)
-//   kStop/kStopEnergy: v += h F; store F (and the per-atom energy)
-//   kQuery:      F and energy to the query buffer in atom-id order only
-//   kRefresh:    store F and the per-atom energy; velocities untouched.
+// atom (lane q takes entries q, q + TPA, ...), summed over the TPA lanes:
+// every lane of the group ends with the sums (grid units in the mixed form)
+// and the atom's position pi.  `pos`: the replica's positions (global or an
+// LDS copy).
 // u(r) = 4 (r^-12 - r^-6) - u(r_c), F_i = 24 (2 r^-14 - r^-8) r_ij for r < r_c
 // (Example section: cutoff 2.5; energy shifted, force truncated).  Every
 // lane of the TPA group must call this (the reduction shuffles).
 template <class P, int MODE, int TPA>
-__device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int ia,
-                                           int q, bool valid, int cur, int64_t step_next, int par)
+__device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa, const RepDev& rd,
+                                          const typename P::pos_t* pos, int ia, int q, bool valid,
+                                          typename P::pos_t& pi, typename P::real& fx, typename P::real& fy,
+                                          typename P::real& fz, typename P::real& e)
 {
     using real = typename P::real;
     constexpr bool kEnergy = (MODE == kStopEnergy || MODE == kQuery || MODE == kRefresh);
-    const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
-    real fx = 0, fy = 0, fz = 0, e = 0;
-    typename P::pos_t pi{};
+    fx = 0;
+    fy = 0;
+    fz = 0;
+    e = 0;
+    pi = typename P::pos_t{};
     if (valid) {
         pi = pos[ia];
         const int nnb = d.nn[rd.base + ia];
-        const uint32_t* __restrict__ nlp = d.nl + rd.nl_base + (size_t)ia * TPA + q;
-        const size_t stride = (size_t)rd.Np * TPA;
+        // list row kk of this lane: the replica's row base (the same for the
+        // whole wave) plus the lane's 32-bit byte offset
+        const char* __restrict__ nlb = reinterpret_cast<const char*>(d.nl + rd.nl_base);
+        const uint32_t eo = (uint32_t)(ia * TPA + q) * (uint32_t)sizeof(uint32_t);
+        const size_t rowb = (size_t)rd.Np * TPA * sizeof(uint32_t);
+        auto entry = [&](int kk) { return *reinterpret_cast<const uint32_t*>(nlb + (size_t)kk * rowb + eo); };
+        // positions by the entries' byte offsets
+        const char* pb = reinterpret_cast<const char*>(pos);
         const int nrow = (nnb - q + TPA - 1) / TPA;
         if constexpr (P::kF64) {
             const double rc2 = rd.rc2d;
             for (int kk = 0; kk < nrow; ++kk) {
-                const uint32_t j = nlp[(size_t)kk * stride];
+                const typename P::pos_t pj = *reinterpret_cast<const typename P::pos_t*>(pb + entry(kk));
                 double dx, dy, dz;
-                P::diff(pi, pos[j], rd, dx, dy, dz);
+                P::diff(pi, pj, rd, dx, dy, dz);
                 const double r2 = dx * dx + dy * dy + dz * dz;
                 if (r2 < rc2) {
                     const double ir2 = 1.0 / r2;
@@ -687,23 +695,32 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
             // (rows past the atom's own entries are read unconditionally -- the
             // list allocation has kListSlackRows rows of slack -- and replaced
             // by the atom itself, which the ok flag then masks)
+            // (the row test of a prefetch is the valid flag of the next four)
+            const uint32_t self = (uint32_t)ia * (uint32_t)sizeof(int4);
             uint32_t jn[U];
+            bool okn[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t ld = nlp[(size_t)u * stride];
-                jn[u] = u < nrow ? ld : (uint32_t)ia;
+                const uint32_t ld = entry(u);
+                okn[u] = u < nrow;
+                jn[u] = okn[u] ? ld : self;
             }
             for (int kk = 0; kk < nrow; kk += U) {
                 int4 pj[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) pj[u] = pos[jn[u]];
+                bool ok[U];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t ld = nlp[(size_t)(kk + U + u) * stride];
-                    jn[u] = kk + U + u < nrow ? ld : (uint32_t)ia;
+                    pj[u] = *reinterpret_cast<const int4*>(pb + jn[u]);
+                    ok[u] = okn[u];
                 }
 #pragma unroll
-                for (int u = 0; u < U; ++u) pair(pj[u], kk + u < nrow);
+                for (int u = 0; u < U; ++u) {
+                    const uint32_t ld = entry(kk + U + u);
+                    okn[u] = kk + U + u < nrow;
+                    jn[u] = okn[u] ? ld : self;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) pair(pj[u], ok[u]);
             }
         }
     }
@@ -714,7 +731,22 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
         fz += __shfl_xor(fz, m, TPA);
         if constexpr (kEnergy) e += __shfl_xor(e, m, TPA);
     }
-    if (!valid || q != 0) return;
+}
+
+// The step epilogue of atom slot ia from its force sums (force_sum), by
+// MODE:
+//   kFused:      v += h F (ends this step), v += h F, x += h v, O, x += h v
+//                (the next step's first half; positions to the other buffer)
+//   kStop/kStopEnergy: v += h F; store F (and the per-atom energy)
+//   kQuery:      F and energy to the query buffer in atom-id order only
+//   kRefresh:    store F and the per-atom energy; velocities untouched.
+template <class P, int MODE>
+__device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int ia,
+                                               int cur, int64_t step_next, int par, const typename P::pos_t& pi,
+                                               typename P::real fx, typename P::real fy, typename P::real fz,
+                                               typename P::real e)
+{
+    using real = typename P::real;
     if constexpr (!P::kF64) {  // grid units -> LJ units
         fx *= rd.sf;
         fy *= rd.sf;
@@ -783,6 +815,19 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
             }
         }
     }
+}
+
+// Force sum and epilogue of atom slot ia by the TPA lanes of its group (the
+// epilogue on lane 0).
+template <class P, int MODE, int TPA>
+__device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int ia,
+                                           int q, bool valid, int cur, int64_t step_next, int par)
+{
+    typename P::pos_t pi;
+    typename P::real fx, fy, fz, e;
+    force_sum<P, MODE, TPA>(d, sa, rd, P::pos(d, cur) + rd.base, ia, q, valid, pi, fx, fy, fz, e);
+    if (!valid || q != 0) return;
+    force_epilogue<P, MODE>(d, sa, rd, r, ia, cur, step_next, par, pi, fx, fy, fz, e);
 }
 
 // Potential energy of replica r in FP64 with the whole workgroup: fixed-

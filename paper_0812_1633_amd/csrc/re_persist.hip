@@ -32,6 +32,8 @@
 // schedule mode joins at injected steps.  Every wait is bounded by the
 // watchdog; a timeout raises the abort flag and every team exits.
 #include "re_device.hpp"
+#include <type_traits>
+
 #include "re_persist.hpp"
 
 namespace re {
@@ -257,6 +259,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     // they fit) copies of the replica's positions and cell starts
     __shared__ int cnt[kPersistLdsWords];
     constexpr int kTabWords = 1024 * list_lds_words<kListLanes>();
+    constexpr int kPosWords = (int)(sizeof(typename P::pos_t) / sizeof(int));
     static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
     __shared__ double dpart[2 * kRedWidth];
@@ -300,12 +303,17 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
     double Ucur = d.U[r];
+    // synchronous form: the next multiple of N_x not below the boundaries
+    // planned so far (advanced as they pass; no 64-bit division per step)
+    int64_t xnext = (s + pa.Nx - 1) / pa.Nx * pa.Nx;
 
-    // plan for the force phase that ends at boundary sn (leader only)
+    // plan for the force phase that ends at boundary sn (leader only;
+    // boundaries are planned in increasing order)
     auto plan = [&](int64_t sn) -> int {
         int c = 0;
         if (cp.mode == kModeSync) {
-            if (sn % pa.Nx == 0) c |= kCtlStop | kCtlJoin;
+            while (xnext < sn) xnext += pa.Nx;
+            if (sn == xnext) c |= kCtlStop | kCtlJoin;
             if (sn >= target) c |= kCtlStop;
         } else if (cp.mode == kModeSchedule) {
             if (asched < cp.A && sn == cp.sched[asched * R + r]) c |= kCtlStop | kCtlJoin;
@@ -438,6 +446,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             const int par = (int)((s + 1) & 1);
             const bool rebuild =
                 __hip_atomic_load(d.flag + (size_t)par * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            bool staged = false;  // this step's positions already copied to LDS
             if (rebuild) {
                 if (leader) reorder_replica<P>(d, rd, r, cur, cnt, part);
                 if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
@@ -447,9 +456,9 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 PT_MARK(2);
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
                 const int32_t* cs = d.cell_start + rd.cell_base;
-                constexpr int kPosWords = (int)(sizeof(typename P::pos_t) / sizeof(int));
                 const int ncs = rd.ncell * rd.ncell * rd.ncell + 1;
-                if (kTabWords + kPosWords * rd.N + ncs <= kPersistLdsWords) {
+                staged = kTabWords + kPosWords * rd.N + ncs <= kPersistLdsWords;
+                if (staged) {
                     // the candidates' positions and the cell starts from LDS
                     typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
                     int32_t* lcs = cnt + kTabWords + kPosWords * rd.N;
@@ -475,18 +484,78 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             }
             const bool stop = (ctl & kCtlStop) != 0;
             const bool with_u = (ctl & kCtlEnergy) != 0;
+            // the force sums read the replica's positions from an LDS copy
+            // when it fits (a gather of 64 lanes from LDS instead of up to 64
+            // L1 lines); the list build may have made it already
+            const typename P::pos_t* gpos = P::pos(d, cur) + rd.base;
+            const bool lds_pos = kTabWords + kPosWords * rd.N <= kPersistLdsWords;
+            typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
+            if (lds_pos && !staged) {
+                for (int k = tid; k < rd.N; k += nt) lpos[k] = gpos[k];
+                __syncthreads();
+            }
             const int apb = nt / TPA;
-            for (int base = i0; base < i1; base += apb) {
-                const int ia = base + tid / TPA;
-                if (!stop)
-                    force_atom<P, kFused, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
-                else if (with_u)
-                    force_atom<P, kStopEnergy, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+            // with TPA > 1 the sums of a pass go through LDS so that the
+            // epilogues run one atom per thread (in the lanes of the atom's
+            // group all but one would idle); LDS free between list builds
+            auto force_pass = [&](auto mode, const typename P::pos_t* fpos) {
+                constexpr int M = decltype(mode)::value;
+                using real = typename P::real;
+                using real4 = typename P::vel_t;
+                real4* lf = reinterpret_cast<real4*>(cnt);
+                typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + apb);
+                for (int base = i0; base < i1; base += apb) {
+                    const int ia = base + tid / TPA;
+                    typename P::pos_t pi;
+                    real fx, fy, fz, e;
+                    force_sum<P, M, TPA>(d, pa.sa, rd, fpos, ia, tid % TPA, ia < i1, pi, fx, fy, fz, e);
+                    if constexpr (TPA == 1) {
+                        if (ia < i1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
+                    } else {
+                        if (tid % TPA == 0 && ia < i1) {
+                            real4 f;
+                            f.x = fx;
+                            f.y = fy;
+                            f.z = fz;
+                            f.w = e;
+                            lf[tid / TPA] = f;
+                            lp[tid / TPA] = pi;
+                        }
+                        __syncthreads();
+                        const int ja = base + tid;
+                        if (tid < apb && ja < i1) {
+                            const real4 f = lf[tid];
+                            force_epilogue<P, M>(d, pa.sa, rd, r, ja, cur, s + 1, par, lp[tid], f.x, f.y, f.z, f.w);
+                        }
+                        if (base + apb < i1) __syncthreads();
+                    }
+                }
+            };
+            static_assert(2 * 512 * sizeof(double4) <= sizeof(int) * kPersistLdsWords, "force stash exceeds LDS");
+            // (separate calls for the two position sources, so that each
+            // inlined copy knows its address space)
+            if (!stop) {
+                if (lds_pos)
+                    force_pass(std::integral_constant<int, kFused>{}, lpos);
                 else
-                    force_atom<P, kStop, TPA>(d, pa.sa, rd, r, ia, tid % TPA, ia < i1, cur, s + 1, par);
+                    force_pass(std::integral_constant<int, kFused>{}, gpos);
+            } else if (with_u) {
+                if (lds_pos)
+                    force_pass(std::integral_constant<int, kStopEnergy>{}, lpos);
+                else
+                    force_pass(std::integral_constant<int, kStopEnergy>{}, gpos);
+            } else {
+                if (lds_pos)
+                    force_pass(std::integral_constant<int, kStop>{}, lpos);
+                else
+                    force_pass(std::integral_constant<int, kStop>{}, gpos);
             }
             if (leader && !stop && tid == 0) ps.ctl[(size_t)((s + 2) & 1) * R + r] = plan(s + 2);
             PT_MARK(4);
+#ifdef RE_PHASE_TIMERS
+            __syncthreads();  // (timers: the workgroup's last wave apart from the team barrier)
+            PT_MARK(7);
+#endif
             if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
                 ok = false;
                 break;
