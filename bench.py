@@ -35,11 +35,11 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # HBM bytes per atom-step of the dominant kernel, from rocprofv3 --pmc
 # FETCH_SIZE and WRITE_SIZE runs of this benchmark with --copy-calibration,
 # each scaled by what the counter reads for the 256 MiB device copy (FETCH_SIZE
-# x 1.99967: it counts half the bytes the copy reads; WRITE_SIZE x 1.0), with
+# x 1.99975: it counts half the bytes the copy reads; WRITE_SIZE x 1.0), with
 # the hash of the kernel sources they were taken with: a changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    ("lj-32x4000", "persistent", 2): dict(fetch=300.4, write=98.1, src="a939309795eae7a1"),
+    ("lj-32x4000", "persistent", 2): dict(fetch=389.8, write=91.5, src="91c7c4284a2bea40"),
 }
 KERNEL_SOURCES = ("re_persist.hip", "re_persist.hpp", "re_device.hpp", "re_internal.hpp", "re_kernels.hip")
 
