@@ -290,3 +290,31 @@ def test_wide_reorder_equals_persistent(relib):
     assert np.array_equal(a[2], b[2])
     for r in range(R):
         assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_reorder_paths_agree(relib, precision):
+    """One ladder of 20000-, 4000- and 1500-atom replicas: with a replica of
+    16384 atoms or more the lockstep engine reorders every replica by
+    grid-wide passes, while the persistent engine reorders the small ones
+    with their atoms held in registers (and builds their lists and forces
+    from LDS copies) and the large one through global scratch.  The same
+    canonical order (cell, then atom id) makes the runs agree bitwise."""
+    N = [20000, 4000, 1500]
+    R, Nx = len(N), 10
+    T = W.ladder(0.8, 1.3, R)
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        e = relib.Engine(N, T, 0.8442, RC, SKIN, DT, Nx, 12, precision=precision, engine=eng,
+                         watchdog_seconds=10)
+        e.step(17)
+        e.step(33)
+        out[eng] = ([e.get_state(r) for r in range(R)], e.query_steps()[1].copy(), e.query_slots().copy(),
+                    e.query_energies().copy())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert np.array_equal(a[1], b[1]) and a[1].min() >= 2
+    assert np.array_equal(a[2], b[2])
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+    assert np.array_equal(a[3], b[3])
