@@ -185,6 +185,17 @@ __device__ __forceinline__ void set_xyz(typename P::vel_t& v, typename P::real x
 }
 
 
+// Rebuild requests.  An atom that has moved more than half the skin since
+// the last list update requests an update before the force of step f by
+// storing rebuild_tag(f) in the word of f's parity; the force of step f
+// rebuilds when that word holds rebuild_tag(f).  A request is never cleared:
+// the tags of other steps do not match, so no clear has to be ordered
+// against the next step's requests.
+__device__ __forceinline__ uint32_t rebuild_tag(int64_t f)
+{
+    return 0x80000000u | (uint32_t)(f & 0x7fffffff);
+}
+
 // ---------------------------------------------------------------------------
 // Phase functions.  Each works on a range of atoms (or a whole replica) of
 // replica r; the lockstep kernels and the persistent engine call them.
@@ -228,7 +239,9 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     P::vel(d)[g] = v;
     real dx, dy, dz;
     P::diff(x, P::xref(d)[g], rd, dx, dy, dz);
-    if (dx * dx + dy * dy + dz * dz > P::lim2(rd)) atomicOr(&d.flag[(size_t)((step + 1) & 1) * sa.R + r], 1u);
+    if (dx * dx + dy * dy + dz * dz > P::lim2(rd))
+        __hip_atomic_store(&d.flag[(size_t)((step + 1) & 1) * sa.R + r], rebuild_tag(step + 1), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Exclusive scan of the ncc cell counts in LDS with the whole workgroup, in
@@ -634,6 +647,7 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
     e = 0;
     pi = typename P::pos_t{};
     if (valid) {
+        const char* pb = reinterpret_cast<const char*>(pos);
         pi = pos[ia];
         const int nnb = d.nn[rd.base + ia];
         // list row kk of this lane: the replica's row base (the same for the
@@ -642,8 +656,6 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
         const uint32_t eo = (uint32_t)(ia * TPA + q) * (uint32_t)sizeof(uint32_t);
         const size_t rowb = (size_t)rd.Np * TPA * sizeof(uint32_t);
         auto entry = [&](int kk) { return *reinterpret_cast<const uint32_t*>(nlb + (size_t)kk * rowb + eo); };
-        // positions by the entries' byte offsets
-        const char* pb = reinterpret_cast<const char*>(pos);
         const int nrow = (nnb - q + TPA - 1) / TPA;
         if constexpr (P::kF64) {
             const double rc2 = rd.rc2d;
@@ -786,7 +798,9 @@ __device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs
             P::vel(d)[g] = v;
             real dx, dy, dz;
             P::diff(x, P::xref(d)[g], rd, dx, dy, dz);
-            if (dx * dx + dy * dy + dz * dz > P::lim2(rd)) atomicOr(&d.flag[(size_t)(par ^ 1) * sa.R + r], 1u);
+            if (dx * dx + dy * dy + dz * dz > P::lim2(rd))
+                __hip_atomic_store(&d.flag[(size_t)(par ^ 1) * sa.R + r], rebuild_tag(step_next + 1),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         } else {
             set_xyz<P>(v, vx, vy, vz);
             P::vel(d)[g] = v;

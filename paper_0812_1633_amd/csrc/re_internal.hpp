@@ -92,7 +92,7 @@ struct DevState {
     double* c2;         // Langevin noise amplitude for the temperature held
     double* alpha;      // velocity factor of the last exchange
     double* U;          // potential energy at the last stopped boundary
-    uint32_t* flag;     // 2 x R list-update flags (indexed by step parity)
+    uint32_t* flag;     // 2 x R list-update requests (by step parity; rebuild_tag of the step)
     int64_t* rebuilds;
     int64_t* steps;
     int64_t* attempts;  // per ladder pair
@@ -121,7 +121,7 @@ struct LaunchCfg {
 // Arguments of one launch of the step kernels.
 struct StepArgs {
     int cur;          // position buffer holding the current positions
-    int par;          // parity of the list-update flags read/cleared by this launch
+    int par;          // parity of the list-update requests read by this launch
     int R;            // replicas in the context
     int r0;           // first replica (per-replica kernels)
     int blk_off;      // first block-table entry (wide kernels)

@@ -61,7 +61,7 @@ __device__ __forceinline__ void rebuild_work(const DevState& d, const StepArgs& 
                                              int& nf)
 {
     const int r = sa.r0 + k;
-    const bool f = sa.force_all || d.flag[(size_t)sa.par * sa.R + r] != 0;
+    const bool f = sa.force_all || d.flag[(size_t)sa.par * sa.R + r] == rebuild_tag(sa.step);
     const int N = d.rep[r].N, c = d.rep[r].ncell;
     nb = f ? (N + kListAPB - 1) / kListAPB : 0;
     na = f ? N : 0;
@@ -295,8 +295,8 @@ __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa, int n
     }
 }
 
-// Force + epilogue; the first block of each replica also marks the list of
-// this parity consumed and the pending velocity factor applied.
+// Force + epilogue; the first block of each replica also marks the pending
+// velocity factor applied.
 template <class P, int MODE, int TPA>
 __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
 {
@@ -305,10 +305,7 @@ __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
     if (r < 0) return;
     const RepDev rd = d.rep[r];
     const int a0 = sa.tab.a0[b];
-    if (MODE != kQuery && a0 == 0 && threadIdx.x == 0) {
-        d.flag[(size_t)sa.par * sa.R + r] = 0u;
-        d.alpha[r] = 1.0;
-    }
+    if (MODE != kQuery && a0 == 0 && threadIdx.x == 0) d.alpha[r] = 1.0;
     const int ia = a0 + (int)(threadIdx.x / TPA);
     force_atom<P, MODE, TPA>(d, sa, rd, r, ia, (int)(threadIdx.x % TPA), ia < rd.N, sa.cur, sa.step, sa.par);
 }

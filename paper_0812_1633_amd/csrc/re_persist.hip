@@ -444,8 +444,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         // ---- steps that end at a fused boundary loop here
         for (;;) {
             const int par = (int)((s + 1) & 1);
-            const bool rebuild =
-                __hip_atomic_load(d.flag + (size_t)par * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            const bool rebuild = __hip_atomic_load(d.flag + (size_t)par * R + r, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT) == rebuild_tag(s + 1);
             bool staged = false;  // this step's positions already copied to LDS
             if (rebuild) {
                 if (leader) reorder_replica<P>(d, rd, r, cur, cnt, part);
@@ -498,21 +498,22 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             // with TPA > 1 the sums of a pass go through LDS so that the
             // epilogues run one atom per thread (in the lanes of the atom's
             // group all but one would idle); LDS free between list builds
-            auto force_pass = [&](auto mode, const typename P::pos_t* fpos) {
+            auto force_pass = [&](auto mode, const typename P::pos_t* fpos, int a0, int a1)
+                                  __attribute__((always_inline)) {
                 constexpr int M = decltype(mode)::value;
                 using real = typename P::real;
                 using real4 = typename P::vel_t;
                 real4* lf = reinterpret_cast<real4*>(cnt);
                 typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + apb);
-                for (int base = i0; base < i1; base += apb) {
+                for (int base = a0; base < a1; base += apb) {
                     const int ia = base + tid / TPA;
                     typename P::pos_t pi;
                     real fx, fy, fz, e;
-                    force_sum<P, M, TPA>(d, pa.sa, rd, fpos, ia, tid % TPA, ia < i1, pi, fx, fy, fz, e);
+                    force_sum<P, M, TPA>(d, pa.sa, rd, fpos, ia, tid % TPA, ia < a1, pi, fx, fy, fz, e);
                     if constexpr (TPA == 1) {
-                        if (ia < i1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
+                        if (ia < a1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
                     } else {
-                        if (tid % TPA == 0 && ia < i1) {
+                        if (tid % TPA == 0 && ia < a1) {
                             real4 f;
                             f.x = fx;
                             f.y = fy;
@@ -523,33 +524,29 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                         }
                         __syncthreads();
                         const int ja = base + tid;
-                        if (tid < apb && ja < i1) {
+                        if (tid < apb && ja < a1) {
                             const real4 f = lf[tid];
                             force_epilogue<P, M>(d, pa.sa, rd, r, ja, cur, s + 1, par, lp[tid], f.x, f.y, f.z, f.w);
                         }
-                        if (base + apb < i1) __syncthreads();
+                        if (base + apb < a1) __syncthreads();
                     }
                 }
             };
             static_assert(2 * 512 * sizeof(double4) <= sizeof(int) * kPersistLdsWords, "force stash exceeds LDS");
-            // (separate calls for the two position sources, so that each
-            // inlined copy knows its address space)
-            if (!stop) {
+            // (separate calls for each position source, so that each inlined
+            // copy knows its address space)
+            auto run = [&](auto mode) __attribute__((always_inline)) {
                 if (lds_pos)
-                    force_pass(std::integral_constant<int, kFused>{}, lpos);
+                    force_pass(mode, lpos, i0, i1);
                 else
-                    force_pass(std::integral_constant<int, kFused>{}, gpos);
-            } else if (with_u) {
-                if (lds_pos)
-                    force_pass(std::integral_constant<int, kStopEnergy>{}, lpos);
-                else
-                    force_pass(std::integral_constant<int, kStopEnergy>{}, gpos);
-            } else {
-                if (lds_pos)
-                    force_pass(std::integral_constant<int, kStop>{}, lpos);
-                else
-                    force_pass(std::integral_constant<int, kStop>{}, gpos);
-            }
+                    force_pass(mode, gpos, i0, i1);
+            };
+            if (!stop)
+                run(std::integral_constant<int, kFused>{});
+            else if (with_u)
+                run(std::integral_constant<int, kStopEnergy>{});
+            else
+                run(std::integral_constant<int, kStop>{});
             if (leader && !stop && tid == 0) ps.ctl[(size_t)((s + 2) & 1) * R + r] = plan(s + 2);
             PT_MARK(4);
 #ifdef RE_PHASE_TIMERS
@@ -561,10 +558,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 break;
             }
             PT_MARK(5);
-            if (leader && tid == 0) {
-                d.flag[(size_t)par * R + r] = 0u;
-                __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
+            if (leader && tid == 0) __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s += 1;
             if (stop) {
                 if (leader) {
