@@ -107,6 +107,12 @@ typedef struct {
                                     counter (k, 0, purpose 5), j >= o = (k mod 2) d
                                     with floor((j - o)/d) even; D = 0 or 1: the
                                     alternating nearest-neighbour pattern    */
+    int debug_delay_us;          /* test hook, persistent engine: after team
+                                    barriers, workgroups picked by a hash of
+                                    (workgroup, step, site) pause for up to
+                                    this many microseconds, so that tests can
+                                    check that results do not depend on the
+                                    timing of the members; 0 = off         */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */

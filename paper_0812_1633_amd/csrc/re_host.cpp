@@ -78,6 +78,7 @@ struct re_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int bar_mode = 0;            // team barrier mode of the persistent engine
+    int delay_us = 0;            // test hook: pauses after team barriers (persistent engine)
     // force-kernel timing with HIP events (re_profile)
     bool prof = false;
     std::vector<hipEvent_t> ev;  // pairs
@@ -570,6 +571,7 @@ static PersistArgs persist_args(re_ctx* c)
     pa.timeout = (uint64_t)(c->watchdog * 1e8);
     pa.bar_mode = c->bar_mode;
     pa.xmaxd = c->xmaxd;
+    pa.delay_ticks = (uint32_t)c->delay_us * 100u;
     return pa;
 }
 
@@ -688,6 +690,8 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.team_barrier != RE_BARRIER_AUTO && o.team_barrier != RE_BARRIER_AGENT)
         return fail(nullptr, RE_EINVAL, "bad team_barrier");
     if (o.exchange_max_distance < 0) return fail(nullptr, RE_EINVAL, "exchange_max_distance must be >= 0");
+    if (o.debug_delay_us < 0 || o.debug_delay_us > 100000)
+        return fail(nullptr, RE_EINVAL, "debug_delay_us must be in [0, 100000]");
     if (o.threads_per_atom && o.threads_per_atom != 1 && o.threads_per_atom != 2 && o.threads_per_atom != 4 &&
         o.threads_per_atom != 8)
         return fail(nullptr, RE_EINVAL, "threads_per_atom must be 1, 2, 4 or 8");
@@ -747,6 +751,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     }
     c->thermo = o.thermostat == RE_SVR ? kThermoSVR : kThermoLangevin;
     c->xmaxd = o.exchange_max_distance > 0 ? o.exchange_max_distance : 1;
+    c->delay_us = o.debug_delay_us;
     // under the velocity rescale the integrator has no friction and no noise
     c->c1 = c->thermo == kThermoSVR ? 1.0 : std::exp(-c->gamma * dt);
     c->svr_c = std::exp(-dt / tau);

@@ -152,6 +152,25 @@ __device__ bool team_sync(const PersistArgs& pa, unsigned* ctr, unsigned& epoch,
     return *s_ok != 0;
 }
 
+// Test hook: after a team barrier, one workgroup in four, picked by a hash
+// of (workgroup, step, site), pauses for a pseudo-random part of
+// delay_ticks (off when 0).  Results must not depend on it.
+__device__ __forceinline__ void maybe_pause(const PersistArgs& pa, int b, int64_t s, int site)
+{
+    if (pa.delay_ticks == 0) return;
+    uint32_t h = (uint32_t)b * 0x9E3779B1u ^ (uint32_t)s * 0x85EBCA77u ^ (uint32_t)site * 0xC2B2AE3Du;
+    h ^= h >> 15;
+    h *= 0x2C1B3C6Du;
+    h ^= h >> 12;
+    if ((h & 3u) != 0) return;
+    if (threadIdx.x == 0) {
+        const uint64_t t0 = clock100();
+        const uint64_t len = (uint64_t)pa.delay_ticks * ((h >> 2) & 15u) / 15u;
+        while (clock100() - t0 < len) __builtin_amdgcn_s_sleep(8);
+    }
+    __syncthreads();
+}
+
 // The exchange join of replica r at its boundary s (energy U) for attempt k,
 // run by the whole leader workgroup.  Returns false on abort.
 __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const CallParams& cp, int r, int64_t k,
@@ -424,6 +443,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             ok = false;
             break;
         }
+        maybe_pause(pa, b, s, 0);
         ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         PT_MARK(0);
         if (ctl & kCtlExit) break;
@@ -436,6 +456,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             ok = false;
             break;
         }
+        maybe_pause(pa, b, s, 1);
         if (leader && tid == 0) {
             d.alpha[r] = 1.0;
             ps.apend[r] = 0;
@@ -453,6 +474,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     ok = false;
                     break;
                 }
+                maybe_pause(pa, b, s, 2);
                 PT_MARK(2);
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
                 const int32_t* cs = d.cell_start + rd.cell_base;
@@ -557,6 +579,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 ok = false;
                 break;
             }
+            maybe_pause(pa, b, s, 3);
             PT_MARK(5);
             if (leader && tid == 0) __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s += 1;

@@ -55,6 +55,7 @@ struct PersistArgs {
     int xmaxd;                // largest ladder distance of an exchange pair (1: nearest neighbours)
     int bar_mode;             // team barrier: 0 agent-scope release + acquire; 1 for teams on one
                               // XCD: stores complete to the shared L2 + agent-scope acquire
+    uint32_t delay_ticks;     // test hook: pauses after team barriers, in 100 MHz ticks (0: off)
 };
 
 hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, int nblk, int nteams, hipStream_t st);

@@ -39,7 +39,8 @@ class Options(C.Structure):
                 ("stream", C.c_void_p), ("watchdog_seconds", C.c_double),
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
                 ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
-                ("team_barrier", C.c_int), ("svr_tau", C.c_double), ("exchange_max_distance", C.c_int)]
+                ("team_barrier", C.c_int), ("svr_tau", C.c_double), ("exchange_max_distance", C.c_int),
+                ("debug_delay_us", C.c_int)]
 
 
 class XLogRec(C.Structure):
@@ -124,13 +125,15 @@ class Engine:
     rescaling, relaxation time svr_tau; 0 = 0.5).
     exchange_max_distance: largest ladder distance of an exchange pair (1:
     alternating nearest neighbours).
+    debug_delay_us: test hook (persistent engine): workgroups pause for up to
+    this many microseconds after team barriers (0: off).
     """
 
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
                  tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0,
-                 exchange_max_distance=1):
+                 exchange_max_distance=1, debug_delay_us=0):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -159,6 +162,7 @@ class Engine:
         o.thermostat = {"langevin": RE_LANGEVIN, "svr": RE_SVR}[thermostat]
         o.svr_tau = float(svr_tau)
         o.exchange_max_distance = int(exchange_max_distance)
+        o.debug_delay_us = int(debug_delay_us)
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))

@@ -318,3 +318,31 @@ def test_reorder_paths_agree(relib, precision):
     for r in range(R):
         assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
     assert np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("precision,team", [("mixed", 8), ("fp64", 3)])
+def test_sync_results_independent_of_timing(relib, precision, team):
+    """Workgroups of the persistent teams paused at random after team
+    barriers (the debug_delay_us hook: one in four, up to 30 us): synchronous
+    runs, with list updates and exchanges, stay bit-identical to the
+    lockstep engine, so no result depends on when the members of a team
+    leave a barrier."""
+    R, N, Nx = 6, 1200, 10
+    T = W.ladder(0.7, 1.6, R)
+    out = {}
+    for eng, delay in (("lockstep", 0), ("persistent", 30)):
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 5, precision=precision, engine=eng,
+                         team_size=team if eng == "persistent" else 0, debug_delay_us=delay,
+                         watchdog_seconds=10)
+        e.step(53)
+        e.step(47)
+        out[eng] = (states(e, R), e.query_slots().copy(), e.query_steps()[1].copy(), e.query_energies().copy())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert a[2].min() >= 5 and np.array_equal(a[2], b[2])
+    assert np.array_equal(a[1], b[1])
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+    assert np.allclose(a[3], b[3], rtol=1e-13, atol=0)
+    with pytest.raises(Exception):
+        relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 5, debug_delay_us=-1)
