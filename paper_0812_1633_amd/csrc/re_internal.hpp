@@ -157,7 +157,6 @@ hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepA
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st);
 hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t seed, double c1sq, int32_t master,
                            int64_t log_cap, int64_t step_all, int max_distance, hipStream_t st);
-hipError_t launch_clear_flags(const DevState& d, int n, hipStream_t st);
 hipError_t launch_set_steps(const DevState& d, int R, int64_t step, hipStream_t st);
 hipError_t launch_test_exchange(const double* U, const double* Tl, int32_t* slot, int R, uint64_t seed,
                                 int64_t attempt, int max_distance, uint8_t* dec, hipStream_t st);

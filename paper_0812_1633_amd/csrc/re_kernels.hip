@@ -440,12 +440,6 @@ __global__ void k_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int
     }
 }
 
-__global__ void k_clear_flags(DevState d, int n)
-{
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) d.flag[i] = 0u;
-}
-
 __global__ void k_set_steps(DevState d, int R, int64_t step)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -544,12 +538,6 @@ hipError_t launch_exchange(const DevState& d, int R, int64_t attempt, uint64_t s
 {
     hipLaunchKernelGGL(k_exchange, dim3(1), dim3(1024), 0, st, d, R, attempt, seed, c1sq, master, log_cap, step_all,
                        max_distance);
-    return hipGetLastError();
-}
-
-hipError_t launch_clear_flags(const DevState& d, int n, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_clear_flags, dim3((n + 255) / 256), dim3(256), 0, st, d, n);
     return hipGetLastError();
 }
 
