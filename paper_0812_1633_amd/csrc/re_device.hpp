@@ -134,8 +134,27 @@ struct PMixed {
         return (float)((uint32_t)x ^ 0x80000000u) * ((float)rd.ncell * 0x1p-32f);
     }
     __device__ static real rc2(const RepDev& rd) { return rd.rc2f; }
-    __device__ static real rl2(const RepDev& rd) { return rd.rl2f; }
     __device__ static real lim2(const RepDev& rd) { return rd.lim2f; }
+    // List-build key: the top 16 bits of each coordinate, x and y packed in
+    // one word, z alone (a grid of 2^16 points per box side)
+    using key_t = uint2;
+    __device__ static key_t list_key(const pos_t& p)
+    {
+        return make_uint2(((uint32_t)p.x >> 16) | ((uint32_t)p.y & 0xffff0000u), (uint32_t)p.z >> 16);
+    }
+    __device__ static key_t list_key(const key_t& k) { return k; }
+    // Within the list radius, on keys: the 16-bit differences wrap (the
+    // minimum image on the coarse grid), their squares sum exactly in 32
+    // bits, and rd.rl2q bounds that sum for every pair closer than the list
+    // radius (each key difference is within one grid step of the true one)
+    __device__ static bool list_close(const key_t& a, const key_t& b, const RepDev& rd)
+    {
+        typedef short short2_t __attribute__((ext_vector_type(2)));
+        const short2_t dxy = __builtin_bit_cast(short2_t, a.x) - __builtin_bit_cast(short2_t, b.x);
+        const short2_t dz = __builtin_bit_cast(short2_t, a.y) - __builtin_bit_cast(short2_t, b.y);
+        const int r2 = __builtin_amdgcn_sdot2(dz, dz, __builtin_amdgcn_sdot2(dxy, dxy, 0, false), false);
+        return (uint32_t)r2 < rd.rl2q;
+    }
 };
 
 struct PF64 {
@@ -172,8 +191,16 @@ struct PF64 {
     }
     __device__ static float cellpos(double x, const RepDev& rd) { return (float)((x / rd.L + 0.5) * (double)rd.ncell); }
     __device__ static real rc2(const RepDev& rd) { return rd.rc2d; }
-    __device__ static real rl2(const RepDev& rd) { return rd.rl2d; }
     __device__ static real lim2(const RepDev& rd) { return rd.lim2d; }
+    // the list build tests FP64 positions directly
+    using key_t = pos_t;
+    __device__ static const key_t& list_key(const pos_t& p) { return p; }
+    __device__ static bool list_close(const key_t& a, const key_t& b, const RepDev& rd)
+    {
+        real dx, dy, dz;
+        diff(a, b, rd, dx, dy, dz);
+        return dx * dx + dy * dy + dz * dz < rd.rl2d;
+    }
 };
 
 template <class P>
@@ -469,29 +496,34 @@ __host__ __device__ constexpr int list_lds_words()
 // so the list holds lane 0's hits, then lane 1's, ..., each in scan order.
 // Entry k of atom i lives at nl[nl_base + ((k / tpa) Np + i) tpa + k % tpa]
 // (tpa a power of two) and holds the byte offset of the neighbour's position
-// from the replica's first slot.  `pos` and `cs` (the replica's positions and cell
-// starts) may be global arrays or copies in LDS.  `lds`: list_lds_words<LPA>()
-// words of this lane.
-template <class P, int LPA>
+// from the replica's first slot.  The distance test is P::list_close on list
+// keys.  `pos`: the replica's positions (global); `keys`: the candidates'
+// keys (P::key_t, e.g. a copy in LDS) or their positions (P::pos_t, keys made
+// on the fly); `cs`: the replica's cell starts (global or a copy in LDS).
+// `lds`: list_lds_words<LPA>() words of this lane.
+template <class P, int LPA, class Src>
 __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, const typename P::pos_t* pos,
-                                          const int32_t* cs, int i, bool act, int q, int tpa, int M, int* lds)
+                                          const Src* keys, const int32_t* cs, int i, bool act, int q, int tpa, int M,
+                                          int* lds)
 {
-    using real = typename P::real;
     constexpr int RPL = ListRowSets<LPA>::kRPL;
     const int nc = rd.ncell;
     const typename P::pos_t pi = pos[act ? i : 0];
+    const typename P::key_t ki = P::list_key(pi);
     // this lane's ranges: flat start lds[2 n], slot offset lds[2 n + 1]
     int T = 0, nr = 0;
     uint64_t bounds = 0;  // bit k: a range other than the first starts at flat index k
     lds[1] = 0;           // offset used by a lane without candidates
+    // (an empty range writes slot nr, which the next range or the end mark
+    // overwrites: at most 2 RPL ranges, so every write stays in the lane's
+    // 4 RPL + 1 words)
     auto add = [&](int a, int b) {
-        if (b > a) {
-            if (nr > 0 && T < 64) bounds |= 1ull << T;
-            lds[2 * nr] = T;
-            lds[2 * nr + 1] = a - T;
-            ++nr;
-            T += b - a;
-        }
+        const bool ne = b > a;
+        if (ne && nr > 0 && T < 64) bounds |= 1ull << T;
+        lds[2 * nr] = T;
+        lds[2 * nr + 1] = a - T;
+        nr += ne ? 1 : 0;
+        T += ne ? b - a : 0;
     };
     if (act) {
         const int cx = P::cellc(pi.x, rd), cy = P::cellc(pi.y, rd), cz = P::cellc(pi.z, rd);
@@ -499,55 +531,65 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         const float fx = fminf(fmaxf(P::cellpos(pi.x, rd) - (float)cx, 0.f), 1.f);
         const float fy = fminf(fmaxf(P::cellpos(pi.y, rd) - (float)cy, 0.f), 1.f);
         const float fz = fminf(fmaxf(P::cellpos(pi.z, rd) - (float)cz, 0.f), 1.f);
+        if (nc >= 5) {
+            // every row slot gives two ranges of cell starts, [cs[ca], cs[cb])
+            // then [cs[cc], cs[cd]) (empty when unused), so that all loads of
+            // cell starts are issued before the first range is written
+            int ca[RPL], cb[RPL], cc[RPL], cd[RPL];
 #pragma unroll
-        for (int w = 0; w < RPL; ++w) {
-            if (nc >= 5) {
-                const int row = (int)((list_row_pack<LPA>(w) >> (5 * q)) & 31u);
-                if (row < 25) {
-                    const int ox = row / 5 - 2, oy = row % 5 - 2;
-                    // distance from the atom to the row's column, in cell units
-                    const float ex = ox > 0 ? (float)ox - fx : (ox < 0 ? fx + (float)(-ox - 1) : 0.f);
-                    const float ey = oy > 0 ? (float)oy - fy : (oy < 0 ? fy + (float)(-oy - 1) : 0.f);
-                    const float h2 = rd.rlcell2 - ex * ex - ey * ey;
-                    if (h2 > 0.f) {
-                        int x = cx + ox, y = cy + oy;
-                        x += x < 0 ? nc : 0;
-                        x -= x >= nc ? nc : 0;
-                        y += y < 0 ? nc : 0;
-                        y -= y >= nc ? nc : 0;
-                        const int rb = (x * nc + y) * nc;
-                        const float h = sqrtf(h2);
-                        const int z0 = cz + max(-2, (int)floorf(fz - h)), z1 = cz + min(2, (int)floorf(fz + h));
-                        if (z0 < 0) {
-                            add(cs[rb + z0 + nc], cs[rb + nc]);
-                            add(cs[rb], cs[rb + z1 + 1]);
-                        } else if (z1 >= nc) {
-                            add(cs[rb + z0], cs[rb + nc]);
-                            add(cs[rb], cs[rb + z1 - nc + 1]);
-                        } else {
-                            add(cs[rb + z0], cs[rb + z1 + 1]);
-                        }
-                    }
-                }
-            } else {
+            for (int w = 0; w < RPL; ++w) {
+                const int row = (int)((list_row_pack<LPA>(w) >> (5 * q)) & 31u);  // 31: no row
+                const int ox = row / 5 - 2, oy = row % 5 - 2;
+                // distance from the atom to the row's column, in cell units
+                const float ex = ox > 0 ? (float)ox - fx : (ox < 0 ? fx + (float)(-ox - 1) : 0.f);
+                const float ey = oy > 0 ? (float)oy - fy : (oy < 0 ? fy + (float)(-oy - 1) : 0.f);
+                const float h2 = rd.rlcell2 - ex * ex - ey * ey;
+                const bool use = row < 25 && h2 > 0.f;
+                int x = cx + ox, y = cy + oy;
+                x += x < 0 ? nc : 0;
+                x -= x >= nc ? nc : 0;
+                y += y < 0 ? nc : 0;
+                y -= y >= nc ? nc : 0;
+                const int rb = (x * nc + y) * nc;
+                const float h = sqrtf(fmaxf(h2, 0.f));
+                const int z0 = cz + max(-2, (int)floorf(fz - h)), z1 = cz + min(2, (int)floorf(fz + h));
+                // z cells z0..z1, wrapped: below 0 the top cells come first,
+                // past nc - 1 the bottom cells come second
+                const bool lo = z0 < 0, hi = z1 >= nc;
+                ca[w] = rb + (lo ? z0 + nc : z0);
+                cb[w] = use ? rb + (lo || hi ? nc : z1 + 1) : ca[w];
+                cc[w] = rb;
+                cd[w] = rb + (use ? (lo ? z1 + 1 : (hi ? z1 - nc + 1 : 0)) : 0);
+            }
+            int va[RPL], vb[RPL], vc[RPL], vd[RPL];
+#pragma unroll
+            for (int w = 0; w < RPL; ++w) {
+                va[w] = cs[ca[w]];
+                vb[w] = cs[cb[w]];
+                vc[w] = cs[cc[w]];
+                vd[w] = cs[cd[w]];
+            }
+#pragma unroll
+            for (int w = 0; w < RPL; ++w) {
+                add(va[w], vb[w]);
+                add(vc[w], vd[w]);
+            }
+        } else {
+#pragma unroll
+            for (int w = 0; w < RPL; ++w) {
                 const int row = q + w * LPA;
                 if (row < nc * nc) add(cs[row * nc], cs[row * nc + nc]);
             }
         }
     }
     lds[2 * nr] = T;
-    const real rl2 = P::rl2(rd);
-    auto test = [&](const typename P::pos_t& pj, int j) {
-        real dx, dy, dz;
-        P::diff(pi, pj, rd, dx, dy, dz);
+    auto test = [&](const Src& kj, int j) {
         // bitwise, so that no load is moved under a branch
-        return (dx * dx + dy * dy + dz * dz < rl2) & (j != i);
+        return P::list_close(ki, P::list_key(kj), rd) & (j != i);
     };
-    // positions by 32-bit byte offsets from the replica's base
-    const char* pbase = reinterpret_cast<const char*>(pos);
-    auto load = [&](uint32_t j) {
-        return *reinterpret_cast<const typename P::pos_t*>(pbase + j * (uint32_t)sizeof(typename P::pos_t));
-    };
+    // keys by 32-bit byte offsets from the replica's base
+    const char* kbase = reinterpret_cast<const char*>(keys);
+    auto load = [&](uint32_t j) { return *reinterpret_cast<const Src*>(kbase + j * (uint32_t)sizeof(Src)); };
     const int T64 = T < 64 ? T : 64;
     uint64_t mk = 0;
     int cnt = 0;
@@ -565,7 +607,7 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         rr[3] = rr[2] + (int)((w >> 2) & 1u);
         ri = rr[3] + (int)((w >> 3) & 1u);
         uint32_t jj[4];
-        typename P::pos_t pj[4];
+        Src pj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) jj[u] = (uint32_t)(k0 + u + lds[2 * rr[u] + 1]);
 #pragma unroll

@@ -812,15 +812,21 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         rd.sf = (float)rd.s;
         rd.inv_sf = (float)rd.inv_s;
         rd.inv_s2f = (float)(rd.inv_s * rd.inv_s);
-        // the list radius carries a 2e-6 relative margin so that FP32
-        // rounding of pair distances can never drop a pair that may come
-        // within r_c before the half-skin test fires
-        const double rcu = r_c * rd.inv_s, rlu = rlist * (1.0 + 2e-6) * rd.inv_s, limu = 0.5 * skin * rd.inv_s;
+        const double rcu = r_c * rd.inv_s, limu = 0.5 * skin * rd.inv_s;
         rd.rc2f = (float)(rcu * rcu);
         rd.near_lo = (float)(rcu * rcu * (1.0 - 0x1p-20));
         rd.near_hi = (float)(rcu * rcu * (1.0 + 0x1p-20));
-        rd.rl2f = (float)(rlu * rlu);
         rd.lim2f = (float)(limu * limu);
+        // mixed list build: coordinates truncated to the top 16 bits differ
+        // from the true ones by less than one step of L 2^-16 each, so a pair
+        // closer than r_list has a key difference shorter than r_list / step
+        // + sqrt 3.  The radius carries a 2e-6 relative margin, so that FP32
+        // rounding in the half-skin test can never let a pair unlisted at the
+        // update come within r_c before the next update.
+        {
+            const double rq = rlist * (1.0 + 2e-6) * 0x1p16 / rd.L + 1.7320508075688772 + 1e-9;
+            rd.rl2q = (uint32_t)std::min(std::ceil(rq * rq), 4294967295.0);
+        }
         rd.rc2d = r_c * r_c;
         rd.rl2d = rlist * rlist * (1.0 + 1e-12);
         rd.lim2d = 0.25 * skin * skin;

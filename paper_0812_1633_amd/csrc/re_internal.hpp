@@ -46,8 +46,8 @@ struct RepDev {
     float inv_s2f;      // 1 / s^2 in FP32
     float rc2f;         // r_c^2 in pair units (FP32)
     float near_lo, near_hi; // FP32 band around rc2f where the exact test decides
-    float rl2f;         // (list radius)^2 in pair units (FP32)
     float lim2f;        // (skin/2)^2 in pair units (FP32)
+    uint32_t rl2q;      // mixed list build: (list radius in units of L 2^-16 + sqrt 3)^2, rounded up
     uint64_t rc2_exact; // ceil((r_c/s)^2): exact integer cutoff test (mixed)
     double rc2d, rl2d, lim2d; // FP64 versions (FP64 form, pair units = LJ units)
 };

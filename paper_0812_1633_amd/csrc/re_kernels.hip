@@ -289,7 +289,7 @@ __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa, int n
         const RepDev rd = d.rep[r];
         const int i = (vb - w.blk[k]) * kListAPB + (int)(threadIdx.x / kListLanes);
         const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
-        list_rows<P, kListLanes>(d, rd, pos, d.cell_start + rd.cell_base, i, i < rd.N, (int)(threadIdx.x % kListLanes),
+        list_rows<P, kListLanes>(d, rd, pos, pos, d.cell_start + rd.cell_base, i, i < rd.N, (int)(threadIdx.x % kListLanes),
                                  sa.tpa, sa.M,
                                  lds + threadIdx.x * W);
     }

@@ -275,14 +275,21 @@ template <class P, int TPA>
 __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 {
     // reorder counts; between reorders the list-build tables, then (when
-    // they fit) copies of the replica's positions and cell starts
+    // they fit) copies of the replica's list keys and cell starts during a
+    // list build, of its positions during the force sums
     __shared__ int cnt[kPersistLdsWords];
+    using key_t = typename P::key_t;
     constexpr int kTabWords = 1024 * list_lds_words<kListLanes>();
     constexpr int kPosWords = (int)(sizeof(typename P::pos_t) / sizeof(int));
+    constexpr int kKeyWords = (int)(sizeof(key_t) / sizeof(int));
+    // list keys that are the positions themselves stay for the force sums
+    constexpr bool kKeyIsPos = std::is_same<key_t, typename P::pos_t>::value;
     static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
     __shared__ double dpart[2 * kRedWidth];
     __shared__ int sh[4];
+    __shared__ int lr_next;  // list build: next batch of atoms to hand out
+    if (threadIdx.x == 0) lr_next = 0;
     const PersistState& ps = pa.st;
     const CallParams& cp = *pa.call;
     const int b = blockIdx.x;
@@ -479,29 +486,40 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 const typename P::pos_t* pos = P::pos(d, cur) + rd.base;
                 const int32_t* cs = d.cell_start + rd.cell_base;
                 const int ncs = rd.ncell * rd.ncell * rd.ncell + 1;
-                staged = kTabWords + kPosWords * rd.N + ncs <= kPersistLdsWords;
-                if (staged) {
-                    // the candidates' positions and the cell starts from LDS
-                    typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
-                    int32_t* lcs = cnt + kTabWords + kPosWords * rd.N;
-                    for (int k = tid; k < rd.N; k += nt) lpos[k] = pos[k];
+                const bool keys_lds = kTabWords + kKeyWords * rd.N + ncs <= kPersistLdsWords;
+                // batches of one wave's atoms go to the waves as they finish
+                // (the lists do not depend on which wave builds them)
+                constexpr int kApw = 64 / kListLanes;  // atoms per wave
+                const int nbatch = (i1 - i0 + kApw - 1) / kApw;
+                auto build = [&](const auto* keys, const int32_t* csp) __attribute__((always_inline)) {
+                    for (;;) {
+                        int bi = 0;
+                        if ((tid & 63) == 0) bi = atomicAdd(&lr_next, 1);
+                        bi = __shfl(bi, 0);
+                        if (bi >= nbatch) break;
+                        const int i = i0 + bi * kApw + (tid & 63) / kListLanes;
+                        list_rows<P, kListLanes>(d, rd, pos, keys, csp, i, i < i1, tid % kListLanes, pa.sa.tpa,
+                                                 pa.sa.M, cnt + tid * list_lds_words<kListLanes>());
+                    }
+                };
+                if (keys_lds) {
+                    // the candidates' keys and the cell starts from LDS
+                    key_t* lkey = reinterpret_cast<key_t*>(cnt + kTabWords);
+                    int32_t* lcs = cnt + kTabWords + kKeyWords * rd.N;
+                    for (int k = tid; k < rd.N; k += nt) lkey[k] = P::list_key(pos[k]);
                     for (int k = tid; k < ncs; k += nt) lcs[k] = cs[k];
                     __syncthreads();
-                    for (int base = i0; base < i1; base += nt / kListLanes) {
-                        const int i = base + tid / kListLanes;
-                        list_rows<P, kListLanes>(d, rd, lpos, lcs, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
-                                                 cnt + tid * list_lds_words<kListLanes>());
-                    }
+                    build((const key_t*)lkey, (const int32_t*)lcs);
+                    staged = kKeyIsPos;
                 } else {
-                    for (int base = i0; base < i1; base += nt / kListLanes) {
-                        const int i = base + tid / kListLanes;
-                        list_rows<P, kListLanes>(d, rd, pos, cs, i, i < i1, tid % kListLanes, pa.sa.tpa, pa.sa.M,
-                                                 cnt + tid * list_lds_words<kListLanes>());
-                    }
+                    build(pos, cs);
                 }
                 // every workgroup builds the lists of its own atoms and then
                 // computes their forces: a workgroup barrier orders the two
+                // (and ends the batch counter's use before its reset; its next
+                // use follows further workgroup barriers)
                 __syncthreads();
+                if (tid == 0) lr_next = 0;
                 PT_MARK(3);
             }
             const bool stop = (ctl & kCtlStop) != 0;
