@@ -169,6 +169,59 @@ def test_forces_exact_cutoff_decision(relib):
     eng.close()
 
 
+def _planted_pairs(L, rc, deltas, seed, min_sep=3.2):
+    """Atoms 2k, 2k+1 at distance rc - deltas[k] along a random direction;
+    atoms of different pairs at least min_sep apart (a dilute gas: every
+    force comes from the planted pairs)."""
+    rng = np.random.default_rng(seed)
+    x = []
+    for d in deltas:
+        while True:
+            a = rng.uniform(-L / 2, L / 2, 3)
+            u = rng.normal(size=3)
+            u /= np.linalg.norm(u)
+            b = a + (rc - d) * u
+            ok = True
+            for y in x:
+                for z in (a, b):
+                    dv = z - y
+                    dv -= L * np.rint(dv / L)
+                    ok &= np.linalg.norm(dv) >= min_sep
+            if ok:
+                x += [a, b]
+                break
+    x = np.array(x)
+    return x - L * np.rint(x / L)
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+@pytest.mark.parametrize("skin", [0.0, 1e-4])
+def test_list_complete_at_radius(relib, precision, skin):
+    """Pairs closer than the list radius by margins from two grid units up
+    to 1e-3, in random directions, with the list radius at (or just past)
+    r_c: the list build keeps every one of them, so each atom feels its
+    partner's force exactly as in the all-pairs oracle."""
+    N, rho = 32, 0.005
+    eng = relib.Engine([N], [1.0], rho, RC, skin, DT, 1000, 1, precision=precision, engine="lockstep")
+    L = eng.query_box()[0]
+    s = W.grid_unit(L)
+    deltas = [2 * s, 1e-6, 3e-6, 1e-5, 3e-5, 1e-4, 2e-4, 3e-4, 4e-4, 5e-4, 6e-4, 8e-4, 1e-3, 2 * s, 1e-5, 5e-4]
+    for seed in range(3):
+        x = W.snap_to_grid(_planted_pairs(L, RC, deltas, 11 + seed), L)
+        eng.set_state(0, x, np.zeros((N, 3)))
+        F, U = eng.compute_forces(0)
+        Fo, Uo, _ = oracle.forces(x, L, RC)
+        # every atom is pulled by its partner (nothing else is within r_c)
+        assert np.all(np.linalg.norm(Fo, axis=1) > 0.03)
+        tol = 1e-5 if precision == "mixed" else 1e-12
+        err = np.linalg.norm(F - Fo, axis=1) / np.linalg.norm(Fo, axis=1)
+        assert err.max() <= tol, (seed, int(err.argmax()), err.max())
+        # (the shifted pair energies nearly cancel: an absolute bound, from
+        # FP32 rounding of 16 unshifted pair energies of about 0.016)
+        assert abs(U - Uo) <= (1e-6 if precision == "mixed" else 1e-12), (U, Uo)
+    eng.close()
+
+
 # --------------------------------------------------------------------------
 # trajectories
 
