@@ -614,10 +614,12 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         for (int u = 0; u < 4; ++u) pj[u] = load(jj[u]);
         uint32_t nib = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) nib |= ((k0 + u < T64) & test(pj[u], (int)jj[u])) ? (1u << u) : 0u;
+        for (int u = 0; u < 4; ++u) nib |= test(pj[u], (int)jj[u]) ? (1u << u) : 0u;
         mk |= (uint64_t)nib << k0;
-        cnt += __popc(nib);
     }
+    // candidates past the lane's end (the last group of four) are dropped
+    if (T64 < 64) mk &= (1ull << T64) - 1ull;
+    cnt = __popcll(mk);
     // candidates past the mask (only with very full rows): walk the ranges
     auto walk = [&](auto&& on_hit) {
         for (int n = 0; n < nr; ++n) {
@@ -627,22 +629,32 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         }
     };
     if (T > 64) walk([&](int) { ++cnt; });
-    // first entry of this lane: the hits of the lanes before it
+    // first entry of this lane: the hits of the lanes before it (an
+    // inclusive scan over the group by row shifts; the groups of LPA lanes
+    // are aligned within the 16-lane rows, and a lane takes no value from
+    // below its group's first lane)
+    // (each shift runs in every lane of the wave, outside any condition: a
+    // lane switched off would hand `old` to the lane above it)
+    static_assert(LPA == 4 || LPA == 8, "list-build groups of 4 or 8 lanes");
     int incl = cnt;
-#pragma unroll
-    for (int sft = 1; sft < LPA; sft <<= 1) {
-        const int v = __shfl_up(incl, sft, LPA);
-        if (q >= sft) incl += v;
+    const int s1 = __builtin_amdgcn_update_dpp(0, incl, 0x111, 0xf, 0xf, false);  // row_shr:1
+    incl += q >= 1 ? s1 : 0;
+    const int s2 = __builtin_amdgcn_update_dpp(0, incl, 0x112, 0xf, 0xf, false);  // row_shr:2
+    incl += q >= 2 ? s2 : 0;
+    if constexpr (LPA == 8) {
+        const int s4 = __builtin_amdgcn_update_dpp(0, incl, 0x114, 0xf, 0xf, false);  // row_shr:4
+        incl += q >= 4 ? s4 : 0;
     }
-    const int tot = __shfl(incl, LPA - 1, LPA);
     int o = incl - cnt;
     // entry o of atom i: word ((o / tpa) Np + i) tpa + o % tpa of the list
+    // (tpa a power of two)
     uint32_t* nl = d.nl + rd.nl_base;
+    const int ltpa = __builtin_ctz((unsigned)tpa);
     const uint32_t jump = (uint32_t)rd.Np * (uint32_t)tpa - (uint32_t)(tpa - 1);
-    uint32_t e = (uint32_t)(o / tpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
+    uint32_t e = ((uint32_t)o >> ltpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
                  (uint32_t)(o & (tpa - 1));
     auto put = [&](int j) {
-        if (o < M) nl[e] = (uint32_t)j * (uint32_t)sizeof(typename P::pos_t);
+        if ((unsigned)o < (unsigned)M) nl[e] = (uint32_t)j * (uint32_t)sizeof(typename P::pos_t);
         ++o;
         e += (o & (tpa - 1)) ? 1u : jump;
     };
@@ -661,9 +673,10 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         put(32 + k + lds[2 * (rhi + __popc(bhi & ((2u << k) - 1u))) + 1]);
     }
     if (T > 64) walk(put);
-    if (act && q == 0) {
-        d.nn[rd.base + i] = tot < M ? tot : M;
-        if (tot > M) atomicOr(d.overflow, 1u);
+    // the group's last lane holds the total
+    if (act && q == LPA - 1) {
+        d.nn[rd.base + i] = incl < M ? incl : M;
+        if (incl > M) atomicOr(d.overflow, 1u);
     }
 }
 
