@@ -75,23 +75,27 @@ def timed_run(R, Nr, exchange, Nx, steps, warmup, seed=1, N=PAPER["N"], **kw):
 def efficiency(Nr_list=(2, 4, 8, 16, 32, 48, 64, 96, 128), steps=500, warmup=100, sync_Nx=5, async_Nx=(1, 3),
                N=PAPER["N"], seed=1):
     """lambda(N_r): steps/s of all replicas with exchanges divided by the
-    same without exchanges, where every replica steps freely for the whole
-    call (asynchronous form with no attempt: the paper's count of steps in a
-    fixed wall-clock time).  Synchronous form at sync_Nx; asynchronous form
-    at each of async_Nx (N_x = 1 is the paper's choice; a larger N_x brings
-    <N_x> near the synchronous stride on one GPU, where a trigger reaches
-    the other replicas within one step).  The ladder reaches
+    same form's steps/s without exchanges (the paper's count of steps in a
+    fixed wall-clock time).  The asynchronous base lets every replica step
+    freely for the whole call; the synchronous base is the synchronous form
+    with no boundary inside the call, so that each lambda measures what the
+    exchanges cost that form.  Synchronous form at sync_Nx; asynchronous
+    form at each of async_Nx (N_x = 1 is the paper's choice; a larger N_x
+    brings <N_x> near the synchronous stride on one GPU, where a trigger
+    reaches the other replicas within one step).  The ladder reaches
     0.7 * 1.0275^(N_r - 1): 22 at N_r = 128, too hot for dt = 0.005 much
     beyond that."""
     from . import re as R
     rows = []
     for Nr in Nr_list:
         base = timed_run(R, Nr, "async", 10**9, steps, warmup, seed, N)
-        row = dict(Nr=int(Nr), base_steps_per_s=base["steps_per_s"])
+        base_sync = timed_run(R, Nr, "sync", 10**9, steps, warmup, seed, N)
+        row = dict(Nr=int(Nr), base_steps_per_s=base["steps_per_s"], base_sync_steps_per_s=base_sync["steps_per_s"])
         runs = [("sync", sync_Nx)] + [("async", nx) for nx in async_Nx]
         for mode, nx in runs:
             t = timed_run(R, Nr, mode, nx, steps, warmup, seed, N)
-            row["%s_Nx%d" % (mode, nx)] = dict(mode=mode, Nx=nx, lam=t["steps_per_s"] / base["steps_per_s"],
+            b = base_sync if mode == "sync" else base
+            row["%s_Nx%d" % (mode, nx)] = dict(mode=mode, Nx=nx, lam=t["steps_per_s"] / b["steps_per_s"],
                                                mean_Nx=t["mean_Nx"], attempts=t["attempts"])
         rows.append(row)
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)

@@ -30,7 +30,7 @@ def test_efficiency_driver(relib):
     res = E.efficiency(Nr_list=(2, 4), steps=100, warmup=20, N=500, async_Nx=(1,))
     assert [r["Nr"] for r in res["rows"]] == [2, 4]
     for row in res["rows"]:
-        assert row["base_steps_per_s"] > 0
+        assert row["base_steps_per_s"] > 0 and row["base_sync_steps_per_s"] > 0
         assert row["sync_Nx5"]["mean_Nx"] == pytest.approx(5.0)
         assert row["async_Nx1"]["mean_Nx"] >= 1.0
         for k in ("sync_Nx5", "async_Nx1"):
