@@ -67,6 +67,25 @@ __device__ unsigned long long g_phase_ticks[1024 * kPhases];
     } while (0)
 #endif
 
+// Copy f(src[k]), k < n, from global memory to LDS with the whole
+// workgroup.  Every thread issues its loads of up to K elements before its
+// first store, so a copy of K * blockDim elements waits for one memory
+// latency, not K (load indices are clamped into the array, so no load
+// depends on a branch).
+template <int K, class D, class S, class F>
+__device__ __forceinline__ void stage_to_lds(D* dst, const S* src, int n, F f)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int base = 0; base < n; base += K * nt) {
+        S v[K];
+#pragma unroll
+        for (int j = 0; j < K; ++j) v[j] = src[min(base + tid + j * nt, n - 1)];
+#pragma unroll
+        for (int j = 0; j < K; ++j)
+            if (base + tid + j * nt < n) dst[base + tid + j * nt] = f(v[j]);
+    }
+}
+
 // Bounded waiting (thread 0 of a workgroup).  The watchdog counts time
 // without progress: any completed force phase anywhere (the heartbeat)
 // restarts it.  On expiry the abort flag is raised.
@@ -284,6 +303,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     constexpr int kKeyWords = (int)(sizeof(key_t) / sizeof(int));
     // list keys that are the positions themselves stay for the force sums
     constexpr bool kKeyIsPos = std::is_same<key_t, typename P::pos_t>::value;
+    // positions staged per thread and round: 64 bytes of registers
+    constexpr int kStageK = (int)(64 / sizeof(typename P::pos_t));
     static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
     __shared__ double dpart[2 * kRedWidth];
@@ -506,8 +527,9 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     // the candidates' keys and the cell starts from LDS
                     key_t* lkey = reinterpret_cast<key_t*>(cnt + kTabWords);
                     int32_t* lcs = cnt + kTabWords + kKeyWords * rd.N;
-                    for (int k = tid; k < rd.N; k += nt) lkey[k] = P::list_key(pos[k]);
-                    for (int k = tid; k < ncs; k += nt) lcs[k] = cs[k];
+                    stage_to_lds<kStageK>(lkey, pos, rd.N,
+                                          [](const typename P::pos_t& p) { return P::list_key(p); });
+                    stage_to_lds<4>(lcs, cs, ncs, [](int c) { return c; });
                     __syncthreads();
                     build((const key_t*)lkey, (const int32_t*)lcs);
                     staged = kKeyIsPos;
@@ -531,7 +553,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             const bool lds_pos = kTabWords + kPosWords * rd.N <= kPersistLdsWords;
             typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
             if (lds_pos && !staged) {
-                for (int k = tid; k < rd.N; k += nt) lpos[k] = gpos[k];
+                stage_to_lds<kStageK>(lpos, gpos, rd.N, [](const typename P::pos_t& p) { return p; });
                 __syncthreads();
             }
             const int apb = nt / TPA;

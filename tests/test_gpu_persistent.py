@@ -320,6 +320,35 @@ def test_reorder_paths_agree(relib, precision):
     assert np.array_equal(a[3], b[3])
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_list_key_staging_paths_agree(relib, precision):
+    """Replicas of 7000, 5000, 9000 and 2000 atoms: in the persistent engine
+    the mixed form's list keys come from LDS for the first two (their
+    positions do not fit there, so the force sums gather from global
+    memory), from global memory for the 9000-atom one, and keys and
+    positions both come from LDS for the smallest; the FP64 form stages only
+    the smallest.  The lockstep engine reads everything from global memory.
+    Synchronous runs with list updates and exchanges agree bitwise."""
+    N = [7000, 5000, 9000, 2000]
+    R, Nx = len(N), 10
+    T = W.ladder(0.8, 1.3, R)
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        e = relib.Engine(N, T, 0.8442, RC, SKIN, DT, Nx, 21, precision=precision, engine=eng,
+                         watchdog_seconds=10)
+        e.step(17)
+        e.step(33)
+        out[eng] = ([e.get_state(r) for r in range(R)], e.query_steps()[1].copy(), e.query_slots().copy(),
+                    e.query_energies().copy())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert np.array_equal(a[1], b[1]) and a[1].min() >= 2
+    assert np.array_equal(a[2], b[2])
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+    assert np.array_equal(a[3], b[3])
+
+
 @pytest.mark.parametrize("precision,team", [("mixed", 8), ("fp64", 3)])
 def test_sync_results_independent_of_timing(relib, precision, team):
     """Workgroups of the persistent teams paused at random after team
