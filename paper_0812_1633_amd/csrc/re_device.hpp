@@ -925,7 +925,19 @@ __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t 
     const double2* q2 = d.svrq + rd.base;
     for (int q = tid; q < kRedWidth; q += nt) {
         double k2 = 0.0, chi = 0.0;
-        for (int i = q; i < rd.N; i += kRedWidth) {
+        int i = q;
+        // (the same additions in the same order, eight loads in flight)
+        for (; i + 7 * kRedWidth < rd.N; i += 8 * kRedWidth) {
+            double2 t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = q2[i + k * kRedWidth];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                k2 += t[k].x;
+                chi += t[k].y;
+            }
+        }
+        for (; i < rd.N; i += kRedWidth) {
             const double2 t = q2[i];
             k2 += t.x;
             chi += t.y;
@@ -962,7 +974,16 @@ __device__ void energy_replica(const DevState& d, const RepDev& rd, int r, doubl
     const typename P::real* e = P::epot(d) + rd.base;
     for (int q = tid; q < kRedWidth; q += nt) {
         double s = 0.0;
-        for (int i = q; i < rd.N; i += kRedWidth) s += (double)e[i];
+        int i = q;
+        // (the same additions in the same order, eight loads in flight)
+        for (; i + 7 * kRedWidth < rd.N; i += 8 * kRedWidth) {
+            typename P::real v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = e[i + k * kRedWidth];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += (double)v[k];
+        }
+        for (; i < rd.N; i += kRedWidth) s += (double)e[i];
         part[q] = s;
     }
     __syncthreads();
