@@ -39,7 +39,7 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # the hash of the kernel sources they were taken with: a changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    ("lj-32x4000", "persistent", 2): dict(fetch=383.2, write=93.5, src="e3c344208a810078"),
+    ("lj-32x4000", "persistent", 2): dict(fetch=373.4, write=93.6, src="a382c7e20fd71167"),
 }
 KERNEL_SOURCES = ("re_persist.hip", "re_persist.hpp", "re_device.hpp", "re_internal.hpp", "re_kernels.hip")
 
