@@ -28,8 +28,8 @@ if ROOT not in sys.path:
 
 METRIC = "atom-steps/s over all replicas (batched mixed vs plain FP64) at stated tol"
 PEAK_FP32_TFLOPS = 157.3  # MI355X published FP32 vector peak (packed FMA)
-# the same unit counts without packed FP32 (this build disables packed FP32
-# instructions): 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
+# the same unit counts without packed FP32 (the library is compiled with packed FP32
+# instructions disabled): 256 CUs x 4 SIMD x 16 lanes x 2 flops x 2.4 GHz
 PEAK_FP32_UNPACKED_TFLOPS = 78.6
 
 # HBM bytes per atom-step of the dominant kernel, from rocprofv3 --pmc
@@ -85,7 +85,7 @@ def main():
                     help="first copy 256 MiB device-to-device (a kernel of known traffic for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build runs every replica on a single MI355X; "
+        print("bench.py measures one GPU: the library runs every replica on a single MI355X; "
               "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
