@@ -53,20 +53,38 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def pair_counts(x, L, rc, rl):
-    """Unique pairs with r < rc and with rc <= r < rl (minimum image), by
-    brute force in blocks (measurement of the algorithmic work)."""
+def pair_counts(x, L, rc, rl, max_exact=8192, sample=4096):
+    """Unique pairs with r < rc and with rc <= r < rl (minimum image), for
+    the algorithmic work: by brute force in blocks up to max_exact atoms;
+    beyond, from the full neighbour counts of `sample` evenly spaced atoms
+    (every pair is seen from both its atoms, so the unique pairs are N times
+    half the mean count)."""
     n_c = n_s = 0
     N = len(x)
-    for a in range(0, N, 512):
-        d = x[a:a + 512, None, :] - x[None, :, :]
+    if N <= max_exact:
+        for a in range(0, N, 512):
+            d = x[a:a + 512, None, :] - x[None, :, :]
+            d -= L * np.round(d / L)
+            r2 = (d * d).sum(-1)
+            idx = np.arange(a, min(N, a + 512))[:, None]
+            upper = np.arange(N)[None, :] > idx
+            n_c += int(((r2 < rc * rc) & upper).sum())
+            n_s += int(((r2 >= rc * rc) & (r2 < rl * rl) & upper).sum())
+        return n_c, n_s
+    pick = np.linspace(0, N - 1, sample).astype(np.int64)
+    for a in range(0, sample, 64):
+        ii = pick[a:a + 64]
+        d = x[ii, None, :] - x[None, :, :]
         d -= L * np.round(d / L)
         r2 = (d * d).sum(-1)
-        idx = np.arange(a, min(N, a + 512))[:, None]
-        upper = np.arange(N)[None, :] > idx
-        n_c += int(((r2 < rc * rc) & upper).sum())
-        n_s += int(((r2 >= rc * rc) & (r2 < rl * rl) & upper).sum())
-    return n_c, n_s
+        other = ii[:, None] != np.arange(N)[None, :]
+        n_c += int(((r2 < rc * rc) & other).sum())
+        n_s += int(((r2 >= rc * rc) & (r2 < rl * rl)).sum())
+    return int(round(n_c * N / (2.0 * sample))), int(round(n_s * N / (2.0 * sample)))
+
+
+def progress(msg):
+    print("bench: " + msg, file=sys.stderr, flush=True)
 
 
 def main():
@@ -116,8 +134,10 @@ def main():
         os.makedirs(os.path.dirname(tune["tune_cache"]), exist_ok=True)
 
     # ---- batched mixed-precision form ------------------------------------
+    progress("%s: %d replicas, %d atoms; creating the context" % (args.workload, len(N), atoms))
     eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune)
     engine_used, tpa_used, team_used = eng.query_config()
+    progress("engine %s, %d lanes per atom; %d warm-up steps" % (engine_used, tpa_used, args.warmup))
     eng.step(args.warmup)
     steps0, reb0 = eng.query_steps()
     torch.cuda.synchronize()
@@ -135,6 +155,7 @@ def main():
     ms_per_step = 1e3 * (t1 - t0) / args.steps
     acc_att, acc_acc = eng.query_acceptance()
 
+    progress("%d timed steps: %.4f ms per step; counting pairs" % (args.steps, ms_per_step))
     # state and forces of two replicas, for the tolerance check of the CPU
     # leg, and their pair counts (the algorithmic work)
     L = eng.query_box()
