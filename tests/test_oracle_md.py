@@ -5,7 +5,8 @@ Pinned by: the FCC/Maxwell-Boltzmann start (lattice distances, zero total
 momentum, exact kinetic temperature), the Verlet-list path being
 bit-identical to the all-pairs definition, second-order energy conservation
 of the gamma = 0 (velocity-Verlet) limit, the exact Ornstein-Uhlenbeck
-variance of the O step, and equipartition under the Langevin thermostat.
+variance of the O step, equipartition under the Langevin thermostat, and
+the virial pressure of a dilute gas against its second virial coefficient.
 """
 import numpy as np
 import pytest
@@ -136,3 +137,45 @@ def test_equipartition_langevin(orc):
     sem = blocks.std(ddof=1) / np.sqrt(len(blocks))
     # BAOAB's kinetic temperature carries an O(dt^2) bias, far below sem here
     assert abs(tk.mean() - T) < 4 * sem + 2e-3, (tk.mean(), sem)
+
+
+def _b2_shifted(T, rc):
+    """Second virial coefficient of the energy-shifted, force-truncated LJ
+    potential, B2 = -2 pi int_0^rc (exp(-u_s(r)/T) - 1) r^2 dr (u_s is
+    continuous at rc and zero beyond, and its force is the truncated LJ
+    force, so it is the potential the dynamics samples), by quadrature."""
+    from scipy.integrate import quad
+
+    ushift = 4.0 * (rc**-12 - rc**-6)
+
+    def f(r):
+        return (np.exp(-(4.0 * (r**-12 - r**-6) - ushift) / T) - 1.0) * r * r
+
+    inner, _ = quad(f, 1e-6, 0.8, limit=200)
+    outer, _ = quad(f, 0.8, rc, limit=200)
+    return -2.0 * np.pi * (inner + outer)
+
+
+def test_low_density_pressure_second_virial(orc):
+    """Dilute LJ gas (rho 0.03, T 1.5) under the Langevin thermostat: the
+    compressibility factor from the pair virial, Z = P/(rho T) =
+    1 + W/(3 N T), matches 1 + B2(T) rho (B2 by quadrature, about -1.78)
+    within 4 sigma of block averages plus 2e-3 for the neglected B3 rho^2
+    term.  A thermostat 20 % off in temperature, forces 1.5 times too large
+    or a doubled virial fail it; an error of about 10 % in the virial alone
+    stays within its tolerance."""
+    N, rho, T = 1000, 0.03, 1.5
+    L = orc.box_length(N, rho)
+    x, v = orc.init_replica(N, L, T, 3, 0)
+    rep = orc.Replica(x, v, L, RC)
+    orc.md(rep, 2000, 0.3, 0.005, 1.0, T, 3, 0)
+    z = []
+    for _ in range(400):
+        orc.md(rep, 25, 0.3, 0.005, 1.0, T, 3, 0)
+        _, _, W = orc.forces(rep.x, L, RC)
+        z.append(1.0 + W / (3.0 * N * T))
+    z = np.array(z)
+    blocks = z.reshape(20, -1).mean(1)
+    sem = blocks.std(ddof=1) / np.sqrt(len(blocks))
+    expect = 1.0 + _b2_shifted(T, RC) * rho
+    assert abs(z.mean() - expect) < 4 * sem + 2e-3, (z.mean(), sem, expect)
