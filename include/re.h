@@ -50,8 +50,9 @@ extern "C" {
                          014101 (2007)): once per step, at the step boundary, every velocity
                          of a replica is multiplied by sqrt(K'/K), K' drawn from the
                          rescale's exact update with N_f = 3N - 3 and relaxation time
-                         svr_tau; gamma is ignored.  Every step then ends at a stopped
-                         boundary (no fused steps): slower than Langevin. */
+                         svr_tau; gamma is ignored.  The rescale needs a replica-wide
+                         sum at the end of every step, so the next step's first half
+                         cannot be fused into the force phase: slower than Langevin. */
 /* precision / form */
 #define RE_MIXED 0 /* positions as 32-bit periodic fixed point, FP32 pair arithmetic,
                       FP32 velocities; FP64 energy sums and rescale factors */

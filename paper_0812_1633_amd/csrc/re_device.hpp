@@ -232,9 +232,10 @@ __device__ __forceinline__ uint32_t rebuild_tag(int64_t f)
 // v = alpha v + h F;  x += h v;  v = c1 v + c2 xi;  x += h v;
 // then the half-skin test against x_ref, which sets the update flag of the
 // next step's parity.  xi: Philox counter (atom id, step, replica, 1).
+// (alpha: the velocity factor applied first, in FP64 as computed)
 template <class P>
-__device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int i,
-                                           int cur, int64_t step, bool apply_alpha)
+__device__ __forceinline__ void start_atom_scaled(const DevState& d, const StepArgs& sa, const RepDev& rd, int r,
+                                                  int i, int cur, int64_t step, double alpha)
 {
     using real = typename P::real;
     const int g = rd.base + i;
@@ -243,7 +244,7 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     typename P::vel_t v = P::vel(d)[g];
     const typename P::vel_t f = P::frc(d)[g];
     const real hh = (real)sa.h;
-    const real a = apply_alpha ? (real)d.alpha[r] : (real)1;
+    const real a = (real)alpha;
     const real c1 = (real)sa.c1;
     const real c2 = (real)d.c2[r];
     real vx = a * v.x + hh * f.x, vy = a * v.y + hh * f.y, vz = a * v.z + hh * f.z;
@@ -269,6 +270,13 @@ __device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa
     if (dx * dx + dy * dy + dz * dz > P::lim2(rd))
         __hip_atomic_store(&d.flag[(size_t)((step + 1) & 1) * sa.R + r], rebuild_tag(step + 1), __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <class P>
+__device__ __forceinline__ void start_atom(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int i,
+                                           int cur, int64_t step, bool apply_alpha)
+{
+    start_atom_scaled<P>(d, sa, rd, r, i, cur, step, apply_alpha ? d.alpha[r] : 1.0);
 }
 
 // Exclusive scan of the ncc cell counts in LDS with the whole workgroup, in
@@ -909,17 +917,19 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
 constexpr int kRedWidth = 256;
 
 // Stochastic velocity rescale of replica r at step boundary s (Example
-// section: the thermostat; Bussi, Donadio and Parrinello 2007), run by one
-// workgroup (part: 2 kRedWidth doubles) after a stopping force phase has
+// section: the thermostat; Bussi, Donadio and Parrinello 2007), computed by
+// one workgroup (part: 2 kRedWidth doubles) after a stopping force phase has
 // left each atom's terms in svrq: K = sum v.v / 2 and the chi-square sum S of
 // N_f - 1 = 3N - 4 squared normals, both in FP64 (fixed slice order); R1 is
 // the first normal of atom 0 (Philox counter (0, s, r, purpose 4)); then
 //   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
-// Kbar = N_f T / 2 at the replica's temperature, and the pending velocity
-// factor is multiplied by sqrt(K'/K) (K = 0: unchanged).
+// Kbar = N_f T / 2 at the replica's temperature.  Returns the velocity
+// factor sqrt(K'/K) (1 when K = 0) to every thread; the fixed order gives
+// every workgroup that computes it the same bits.  Ends with a workgroup
+// barrier.
 template <class P>
-__device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
-                            double* part)
+__device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
+                             double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const double2* q2 = d.svrq + rd.base;
@@ -959,11 +969,27 @@ __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t 
         normals3d(draw(seed, 0u, (uint32_t)s, (uint32_t)r, kPurposeSVR), R1, z1, z2);
         const double Nf = 3.0 * rd.N - 3.0;
         const double Kbar = 0.5 * Nf * d.Tl[d.slot[r]];
+        double f = 1.0;
         if (K > 0.0) {
             const double Kn = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
-            d.alpha[r] *= sqrt(Kn / K);
+            f = sqrt(Kn / K);
         }
+        part[1] = f;
     }
+    __syncthreads();
+    const double f = part[1];
+    __syncthreads();
+    return f;
+}
+
+// The velocity rescale of svr_factor folded into the replica's pending
+// velocity factor (alpha *= sqrt(K'/K)), by one workgroup.
+template <class P>
+__device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
+                            double* part)
+{
+    const double f = svr_factor<P>(d, rd, r, s, seed, c, part);
+    if (threadIdx.x == 0) d.alpha[r] *= f;
     __syncthreads();
 }
 

@@ -475,7 +475,7 @@ static int plan_persistent(re_ctx* c, int team_opt)
     int dev = 0, cus = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(c, persist_occupancy(c->prec == RE_FP64, c->cfg.tpa, &occ));
+    HIPCHK(c, persist_occupancy(c->prec == RE_FP64, c->cfg.tpa, c->thermo == kThermoSVR, &occ));
     const int cap = cus * std::max(0, occ);
     const int R = c->R;
     c->pers_ok = false;

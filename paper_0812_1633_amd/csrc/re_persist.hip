@@ -289,8 +289,13 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
 // at that boundary, bit 2 leave the run here, bit 3 the stop needs the
 // potential energy (a stop for the velocity rescale alone does not)
 constexpr int kCtlStop = 1, kCtlJoin = 2, kCtlExit = 4, kCtlEnergy = 8;
+// a step that stops only for the velocity rescale: its force phase stops,
+// and the rescale and the next step's first half follow inside the step loop
+constexpr int kCtlSVR = 16;
 
-template <class P, int TPA>
+// SVR: compiled for the stochastic velocity rescale (whose steps end inside
+// the step loop, see kCtlSVR); the Langevin form carries none of that code.
+template <class P, int TPA, bool SVR>
 __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
 {
     // reorder counts; between reorders the list-build tables, then (when
@@ -380,8 +385,14 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         // the asynchronous form every stop: a replica may find at the
         // boundary that it parks, and then joins attempts with its U)
         if ((c & kCtlStop) || cp.mode == kModeAsync) c |= kCtlEnergy;
-        // the velocity rescale needs every step to end at a stopped boundary
-        if (pa.sa.thermo == kThermoSVR) c |= kCtlStop;
+        // the velocity rescale needs the velocities of every atom at the end of
+        // every step: the force phase stops (a step that stops for nothing
+        // else is marked kCtlSVR and goes on inside the step loop)
+        if constexpr (SVR) {
+            if (!(c & kCtlStop)) c |= kCtlStop | kCtlSVR;
+        } else if (pa.sa.thermo == kThermoSVR) {
+            c |= kCtlStop;
+        }
         return c;
     };
 
@@ -623,6 +634,27 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             PT_MARK(5);
             if (leader && tid == 0) __hip_atomic_fetch_add(ps.beat, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s += 1;
+            if constexpr (SVR) {
+            if (stop && (ctl & kCtlSVR)) {
+                // the velocity rescale without leaving the step loop: every
+                // member computes the factor (the same bits in each), then the
+                // first half of the next step for its own atoms with the
+                // pending factor (1 between exchanges) times it applied
+                const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, dpart);
+                const double a64 = d.alpha[r] * fct;
+                for (int i = i0 + tid; i < i1; i += nt) start_atom_scaled<P>(d, pa.sa, rd, r, i, cur, s, a64);
+                if (leader && tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = plan(s + 1);
+                if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
+                    ok = false;
+                    break;
+                }
+                maybe_pause(pa, b, s, 6);
+                PT_MARK(1);
+                ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT);
+                continue;
+            }
+            }
             if (stop) {
                 if (leader) {
                     if (with_u) {
@@ -680,14 +712,14 @@ __global__ void k_persist_prepare(DevState d, PersistArgs pa, int nteams)
     }
 }
 
-template <class P>
+template <class P, bool SVR>
 static hipError_t persist_t(const DevState& d, const PersistArgs& pa, int nblk, hipStream_t st)
 {
     switch (pa.sa.tpa) {
-    case 1: hipLaunchKernelGGL((k_persist<P, 1>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
-    case 2: hipLaunchKernelGGL((k_persist<P, 2>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
-    case 4: hipLaunchKernelGGL((k_persist<P, 4>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
-    case 8: hipLaunchKernelGGL((k_persist<P, 8>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 1: hipLaunchKernelGGL((k_persist<P, 1, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 2: hipLaunchKernelGGL((k_persist<P, 2, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 4: hipLaunchKernelGGL((k_persist<P, 4, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
+    case 8: hipLaunchKernelGGL((k_persist<P, 8, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -699,7 +731,9 @@ hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, i
     hipLaunchKernelGGL(k_persist_prepare, dim3((n + 255) / 256), dim3(256), 0, st, d, pa, nteams);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return fp64 ? persist_t<PF64>(d, pa, nblk, st) : persist_t<PMixed>(d, pa, nblk, st);
+    const bool svr = pa.sa.thermo == kThermoSVR;
+    if (fp64) return svr ? persist_t<PF64, true>(d, pa, nblk, st) : persist_t<PF64, false>(d, pa, nblk, st);
+    return svr ? persist_t<PMixed, true>(d, pa, nblk, st) : persist_t<PMixed, false>(d, pa, nblk, st);
 }
 
 #ifdef RE_PHASE_TIMERS
@@ -714,24 +748,21 @@ extern "C" int re_debug_phase_ticks(unsigned long long* out, int nblk)
 }
 #endif
 
-hipError_t persist_occupancy(bool fp64, int tpa, int* blocks_per_cu)
+template <class P, bool SVR>
+static const void* persist_kernel(int tpa)
 {
-    const void* f = nullptr;
-    if (fp64) {
-        switch (tpa) {
-        case 1: f = (const void*)k_persist<PF64, 1>; break;
-        case 2: f = (const void*)k_persist<PF64, 2>; break;
-        case 4: f = (const void*)k_persist<PF64, 4>; break;
-        default: f = (const void*)k_persist<PF64, 8>; break;
-        }
-    } else {
-        switch (tpa) {
-        case 1: f = (const void*)k_persist<PMixed, 1>; break;
-        case 2: f = (const void*)k_persist<PMixed, 2>; break;
-        case 4: f = (const void*)k_persist<PMixed, 4>; break;
-        default: f = (const void*)k_persist<PMixed, 8>; break;
-        }
+    switch (tpa) {
+    case 1: return (const void*)k_persist<P, 1, SVR>;
+    case 2: return (const void*)k_persist<P, 2, SVR>;
+    case 4: return (const void*)k_persist<P, 4, SVR>;
+    default: return (const void*)k_persist<P, 8, SVR>;
     }
+}
+
+hipError_t persist_occupancy(bool fp64, int tpa, bool svr, int* blocks_per_cu)
+{
+    const void* f = fp64 ? (svr ? persist_kernel<PF64, true>(tpa) : persist_kernel<PF64, false>(tpa))
+                         : (svr ? persist_kernel<PMixed, true>(tpa) : persist_kernel<PMixed, false>(tpa));
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 1024, 0);
 }
 
