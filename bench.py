@@ -39,7 +39,7 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # the hash of the kernel sources they were taken with: a changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    ("lj-32x4000", "persistent", 2): dict(fetch=373.4, write=93.6, src="a382c7e20fd71167"),
+    ("lj-32x4000", "persistent", 2): dict(fetch=374.9, write=93.3, src="b9463e624eb06146"),
 }
 KERNEL_SOURCES = ("re_persist.hip", "re_persist.hpp", "re_device.hpp", "re_internal.hpp", "re_kernels.hip")
 
@@ -185,7 +185,7 @@ def main():
                 "hbm_GBps_at_traffic": (traffic / (k_ms * 1e-3) / 1e9) if traffic and k_ms > 0 else None,
                 "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": (achieved / PEAK_FP32_UNPACKED_TFLOPS) if achieved else None,
-                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed,%d>" % tpa_used,
+                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed,%d,false>" % tpa_used,
                 "kernel_ms": k_ms, "launches_timed": k_n, "atom_steps_per_launch": atom_steps_launch,
                 "flop_per_atom_step": float(flop_per_atom), "kernel_src": src}
     eng.close()
