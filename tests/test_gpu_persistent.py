@@ -349,20 +349,23 @@ def test_list_key_staging_paths_agree(relib, precision):
     assert np.array_equal(a[3], b[3])
 
 
-@pytest.mark.parametrize("precision,team", [("mixed", 8), ("fp64", 3)])
-def test_sync_results_independent_of_timing(relib, precision, team):
+@pytest.mark.parametrize("precision,team,thermostat", [("mixed", 8, "langevin"), ("fp64", 3, "langevin"),
+                                                     ("mixed", 8, "svr"), ("fp64", 3, "svr")])
+def test_sync_results_independent_of_timing(relib, precision, team, thermostat):
     """Workgroups of the persistent teams paused at random after team
     barriers (the debug_delay_us hook: one in four, up to 30 us): synchronous
     runs, with list updates and exchanges, stay bit-identical to the
     lockstep engine, so no result depends on when the members of a team
-    leave a barrier."""
+    leave a barrier.  Under the velocity rescale every member computes the
+    rescale factor after the force phase's barrier and the next first half
+    ends at another one."""
     R, N, Nx = 6, 1200, 10
     T = W.ladder(0.7, 1.6, R)
     out = {}
     for eng, delay in (("lockstep", 0), ("persistent", 30)):
         e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 5, precision=precision, engine=eng,
                          team_size=team if eng == "persistent" else 0, debug_delay_us=delay,
-                         watchdog_seconds=10)
+                         watchdog_seconds=10, thermostat=thermostat, svr_tau=0.2)
         e.step(53)
         e.step(47)
         out[eng] = (states(e, R), e.query_slots().copy(), e.query_steps()[1].copy(), e.query_energies().copy())
