@@ -815,11 +815,14 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
 //   kStop/kStopEnergy: v += h F; store F (and the per-atom energy)
 //   kQuery:      F and energy to the query buffer in atom-id order only
 //   kRefresh:    store F and the per-atom energy; velocities untouched.
+// (v0: the atom's velocity, xr0: its x_ref (read in kFused only), both
+// loaded by the caller)
 template <class P, int MODE>
-__device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int ia,
-                                               int cur, int64_t step_next, int par, const typename P::pos_t& pi,
-                                               typename P::real fx, typename P::real fy, typename P::real fz,
-                                               typename P::real e)
+__device__ __forceinline__ void force_epilogue_v(const DevState& d, const StepArgs& sa, const RepDev& rd, int r,
+                                                 int ia, int cur, int64_t step_next, int par,
+                                                 const typename P::pos_t& pi, typename P::real fx,
+                                                 typename P::real fy, typename P::real fz, typename P::real e,
+                                                 typename P::vel_t v0, const typename P::pos_t& xr0)
 {
     using real = typename P::real;
     if constexpr (!P::kF64) {  // grid units -> LJ units
@@ -836,7 +839,7 @@ __device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs
         o[3] = (double)e;
     } else {
         const real hh = MODE == kRefresh ? (real)0 : (real)sa.h;
-        typename P::vel_t v = P::vel(d)[g];
+        typename P::vel_t v = v0;
         real vx = v.x + hh * fx, vy = v.y + hh * fy, vz = v.z + hh * fz;
         if constexpr (MODE == kFused) {
             const real c1 = (real)sa.c1;
@@ -860,7 +863,7 @@ __device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs
             set_xyz<P>(v, vx, vy, vz);
             P::vel(d)[g] = v;
             real dx, dy, dz;
-            P::diff(x, P::xref(d)[g], rd, dx, dy, dz);
+            P::diff(x, xr0, rd, dx, dy, dz);
             if (dx * dx + dy * dy + dz * dz > P::lim2(rd))
                 __hip_atomic_store(&d.flag[(size_t)(par ^ 1) * sa.R + r], rebuild_tag(step_next + 1),
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -892,6 +895,20 @@ __device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs
             }
         }
     }
+}
+
+// The epilogue with the atom's velocity and x_ref loaded here.
+template <class P, int MODE>
+__device__ __forceinline__ void force_epilogue(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int ia,
+                                               int cur, int64_t step_next, int par, const typename P::pos_t& pi,
+                                               typename P::real fx, typename P::real fy, typename P::real fz,
+                                               typename P::real e)
+{
+    typename P::vel_t v{};
+    typename P::pos_t xr{};
+    if constexpr (MODE != kQuery) v = P::vel(d)[rd.base + ia];
+    if constexpr (MODE == kFused) xr = P::xref(d)[rd.base + ia];
+    force_epilogue_v<P, MODE>(d, sa, rd, r, ia, cur, step_next, par, pi, fx, fy, fz, e, v, xr);
 }
 
 // Force sum and epilogue of atom slot ia by the TPA lanes of its group (the

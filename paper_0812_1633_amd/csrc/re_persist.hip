@@ -586,6 +586,17 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     if constexpr (TPA == 1) {
                         if (ia < a1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
                     } else {
+                        // the velocity and x_ref of this thread's epilogue atom
+                        // are loaded before the barrier, so that their latency
+                        // overlaps the wait for the other waves' sums
+                        const int ja = base + tid;
+                        const bool epi = tid < apb && ja < a1;
+                        real4 v0{};
+                        typename P::pos_t xr0{};
+                        if (epi) {
+                            if constexpr (M != kQuery) v0 = P::vel(d)[rd.base + ja];
+                            if constexpr (M == kFused) xr0 = P::xref(d)[rd.base + ja];
+                        }
                         if (tid % TPA == 0 && ia < a1) {
                             real4 f;
                             f.x = fx;
@@ -596,10 +607,10 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                             lp[tid / TPA] = pi;
                         }
                         __syncthreads();
-                        const int ja = base + tid;
-                        if (tid < apb && ja < a1) {
+                        if (epi) {
                             const real4 f = lf[tid];
-                            force_epilogue<P, M>(d, pa.sa, rd, r, ja, cur, s + 1, par, lp[tid], f.x, f.y, f.z, f.w);
+                            force_epilogue_v<P, M>(d, pa.sa, rd, r, ja, cur, s + 1, par, lp[tid], f.x, f.y, f.z, f.w,
+                                                   v0, xr0);
                         }
                         if (base + apb < a1) __syncthreads();
                     }
