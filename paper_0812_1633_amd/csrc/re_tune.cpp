@@ -156,15 +156,21 @@ int tune_run(int R, const int32_t* N, const double* T, double rho, double rc, do
                 continue;
             }
             double ms = 1e300;
-            // warm up, estimate, then time about a quarter of a second
+            // estimate, warm up for about 0.1 s (past the melting of the
+            // start lattice, whose list updates come at another rate), then
+            // time about half a second
             using clk = std::chrono::steady_clock;
             std::vector<double> Uq(R);  // a query synchronises the context's stream
             bool ok = re_step(c, 4) == RE_OK;
             auto t0 = clk::now();
             ok = ok && re_step(c, 4) == RE_OK && re_query_energies(c, Uq.data()) == RE_OK;
-            const double est = std::chrono::duration<double, std::milli>(clk::now() - t0).count() / 4.0;
+            const double est = std::max(std::chrono::duration<double, std::milli>(clk::now() - t0).count() / 4.0, 1e-3);
             if (ok) {
-                const int k = std::max(8, std::min(400, (int)(250.0 / std::max(est, 1e-3))));
+                const int warm = std::max(20, std::min(1000, (int)(100.0 / est)));
+                ok = re_step(c, warm) == RE_OK && re_query_energies(c, Uq.data()) == RE_OK;
+            }
+            if (ok) {
+                const int k = std::max(8, std::min(4000, (int)(500.0 / est)));
                 t0 = clk::now();
                 ok = re_step(c, k) == RE_OK && re_query_energies(c, Uq.data()) == RE_OK;
                 ms = std::chrono::duration<double, std::milli>(clk::now() - t0).count() / k;
