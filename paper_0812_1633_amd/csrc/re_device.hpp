@@ -772,11 +772,22 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
             // by the atom itself, which the ok flag then masks)
             // (the row test of a prefetch is the valid flag of the next four)
             const uint32_t self = (uint32_t)ia * (uint32_t)sizeof(int4);
+            // the list words through a buffer resource over the replica's
+            // block: the row offset goes in a scalar register and the lane's
+            // in a 32-bit vector register, so an index load needs no vector
+            // address arithmetic (the host keeps a block under 2^32 bytes)
+            const __amdgpu_buffer_rsrc_t nlr = __builtin_amdgcn_make_buffer_rsrc(
+                (void*)nlb, (short)0, (int)((uint32_t)rd.Np * (uint32_t)sa.M * (uint32_t)sizeof(uint32_t)),
+                0x00020000);  // (descriptor word 3 of gfx9: 32-bit elements)
+            const uint32_t rowb32 = (uint32_t)rowb;
+            auto bentry = [&](int kk) {
+                return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(nlr, (int)eo, (int)((uint32_t)kk * rowb32), 0);
+            };
             uint32_t jn[U];
             bool okn[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t ld = entry(u);
+                const uint32_t ld = bentry(u);
                 okn[u] = u < nrow;
                 jn[u] = okn[u] ? ld : self;
             }
@@ -790,7 +801,7 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
-                    const uint32_t ld = entry(kk + U + u);
+                    const uint32_t ld = bentry(kk + U + u);
                     okn[u] = kk + U + u < nrow;
                     jn[u] = okn[u] ? ld : self;
                 }

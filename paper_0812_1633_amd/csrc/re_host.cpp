@@ -796,10 +796,11 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         c->cells_max = std::max(c->cells_max, nc * nc * nc);
         rd.nl_base = nl;
         nl += (int64_t)rd.Np * c->cfg.M;
-        // list words of one replica are addressed with 32-bit offsets
-        if ((int64_t)rd.Np * c->cfg.M >= ((int64_t)1 << 31)) {
+        // list words of one replica are addressed with 32-bit byte offsets
+        // (with the slack rows read past the block)
+        if (((int64_t)rd.Np * c->cfg.M + (int64_t)kListSlackRows * 8 * rd.Np) * 4 >= ((int64_t)1 << 32)) {
             delete c;
-            return fail(nullptr, RE_EINVAL, "replica %d: %lld list entries exceed 2^31", r,
+            return fail(nullptr, RE_EINVAL, "replica %d: %lld list entries exceed 2^30", r,
                         (long long)rd.Np * c->cfg.M);
         }
         if (c->prec == RE_MIXED) {

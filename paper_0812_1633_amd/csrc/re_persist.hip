@@ -560,14 +560,24 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             // the force sums read the replica's positions from an LDS copy
             // when it fits (a gather of 64 lanes from LDS instead of up to 64
             // L1 lines); the list build may have made it already
+            // (the mixed form's copy starts at the array's first word, so that
+            // a neighbour's LDS address is its list word itself, with no base
+            // to add; the stash of the force sums follows it.  The FP64 form
+            // keeps the copy where the list build left its keys.)
             const typename P::pos_t* gpos = P::pos(d, cur) + rd.base;
-            const bool lds_pos = kTabWords + kPosWords * rd.N <= kPersistLdsWords;
-            typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kTabWords);
+            const int apb = nt / TPA;
+            constexpr int kPosAt = kKeyIsPos ? kTabWords : 0;
+            constexpr int kStashWords =
+                (int)((sizeof(typename P::vel_t) + sizeof(typename P::pos_t)) / sizeof(int)) * (1024 / TPA);
+            const int pos_words = (kPosWords * rd.N + 7) & ~7;  // (32-byte aligned stash)
+            const bool lds_pos = kKeyIsPos ? kTabWords + kPosWords * rd.N <= kPersistLdsWords
+                                           : (TPA == 1 ? 0 : kStashWords) + pos_words <= kPersistLdsWords;
+            const int stash_at = kKeyIsPos || !lds_pos ? 0 : pos_words;
+            typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kPosAt);
             if (lds_pos && !staged) {
                 stage_to_lds<kStageK>(lpos, gpos, rd.N, [](const typename P::pos_t& p) { return p; });
                 __syncthreads();
             }
-            const int apb = nt / TPA;
             // with TPA > 1 the sums of a pass go through LDS so that the
             // epilogues run one atom per thread (in the lanes of the atom's
             // group all but one would idle); LDS free between list builds
@@ -576,7 +586,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 constexpr int M = decltype(mode)::value;
                 using real = typename P::real;
                 using real4 = typename P::vel_t;
-                real4* lf = reinterpret_cast<real4*>(cnt);
+                real4* lf = reinterpret_cast<real4*>(cnt + stash_at);
                 typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + apb);
                 for (int base = a0; base < a1; base += apb) {
                     const int ia = base + tid / TPA;
