@@ -323,12 +323,11 @@ def test_reorder_paths_agree(relib, precision):
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
 def test_list_key_staging_paths_agree(relib, precision):
     """Replicas of 7000, 5000, 9000 and 2000 atoms: in the persistent engine
-    the mixed form's list keys come from LDS for the first two (their
-    positions do not fit there, so the force sums gather from global
-    memory), from global memory for the 9000-atom one, and keys and
-    positions both come from LDS for the smallest; the FP64 form stages only
-    the smallest.  The lockstep engine reads everything from global memory.
-    Synchronous runs with list updates and exchanges agree bitwise."""
+    (4 lanes per atom) the mixed form takes the list keys and the force sums'
+    positions from LDS copies for all but the 9000-atom replica, which reads
+    both from global memory; the FP64 form stages only the smallest.  The
+    lockstep engine reads everything from global memory.  Synchronous runs
+    with list updates and exchanges agree bitwise."""
     N = [7000, 5000, 9000, 2000]
     R, Nx = len(N), 10
     T = W.ladder(0.8, 1.3, R)
@@ -347,6 +346,31 @@ def test_list_key_staging_paths_agree(relib, precision):
     for r in range(R):
         assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
     assert np.array_equal(a[3], b[3])
+
+
+@pytest.mark.parametrize("tpa,nfit", [(2, 8192), (4, 8704)])
+def test_position_copy_at_its_limit(relib, tpa, nfit):
+    """The mixed form's LDS copy of the positions (16 B per atom) and the
+    stash of per-atom sums (32 B per atom of a pass: 1024 / tpa atoms) share
+    the persistent workgroup's 144 KiB: replicas of nfit atoms fill it
+    exactly, one atom more reads the positions from global memory.  Both
+    agree bitwise with the lockstep engine over list updates and
+    exchanges."""
+    N = [nfit, nfit + 1]
+    R, Nx = len(N), 10
+    T = W.ladder(0.8, 1.3, R)
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        e = relib.Engine(N, T, 0.8442, RC, SKIN, DT, Nx, 5, engine=eng, threads_per_atom=tpa,
+                         watchdog_seconds=10)
+        e.step(40)
+        out[eng] = ([e.get_state(r) for r in range(R)], e.query_steps()[1].copy(), e.query_energies().copy())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert np.array_equal(a[1], b[1]) and a[1].min() >= 2
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+    assert np.array_equal(a[2], b[2])
 
 
 @pytest.mark.parametrize("precision,team,thermostat", [("mixed", 8, "langevin"), ("fp64", 3, "langevin"),
