@@ -143,8 +143,10 @@ typedef struct {
  * more than skin/2; Example section); dt: time step; N_x: exchange stride
  * (Implementation section); seed: Philox4x32-10 key.
  * Errors: RE_EINVAL for R < 1, any N < 2, a non-ascending or non-positive
- * ladder, rho <= 0, r_c <= 0, skin < 0, dt <= 0, N_x < 1, or r_c + skin >= L/2
- * for some replica; RE_ENOMEM; RE_EDEVICE.  *out is NULL on failure.
+ * ladder, rho <= 0, r_c <= 0, skin < 0, dt <= 0, N_x < 1, r_c + skin >= L/2
+ * for some replica, or a replica whose neighbour-list block (with the rows
+ * read past it) would reach 2^32 bytes (its words are addressed with 32-bit
+ * byte offsets); RE_ENOMEM; RE_EDEVICE.  *out is NULL on failure.
  */
 int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladder,
               double rho, double r_c, double skin, double dt, int N_x, uint64_t seed,

@@ -798,10 +798,11 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         nl += (int64_t)rd.Np * c->cfg.M;
         // list words of one replica are addressed with 32-bit byte offsets
         // (with the slack rows read past the block)
-        if (((int64_t)rd.Np * c->cfg.M + (int64_t)kListSlackRows * 8 * rd.Np) * 4 >= ((int64_t)1 << 32)) {
+        const int64_t nl_bytes = ((int64_t)rd.Np * c->cfg.M + (int64_t)kListSlackRows * 8 * rd.Np) * 4;
+        if (nl_bytes >= ((int64_t)1 << 32)) {
             delete c;
-            return fail(nullptr, RE_EINVAL, "replica %d: %lld list entries exceed 2^30", r,
-                        (long long)rd.Np * c->cfg.M);
+            return fail(nullptr, RE_EINVAL, "replica %d: its neighbour-list block (%lld bytes) reaches 2^32 bytes", r,
+                        (long long)nl_bytes);
         }
         if (c->prec == RE_MIXED) {
             rd.s = rd.L * 0x1p-32;

@@ -46,6 +46,7 @@ def test_exports_every_declared_symbol(R):
     (dict(N=[256], T=[1.0], dt=0.0), "dt"),
     (dict(N=[256], T=[1.0], Nx=0), "N_x"),
     (dict(N=[256], T=[1.0], rho=-1.0), "rho"),
+    (dict(N=[6_000_000], T=[1.0]), "2^32 bytes"),
 ])
 def test_invalid_arguments(R, kw, msg):
     args = dict(rho=0.8442, rc=2.5, skin=0.3, dt=0.005, Nx=10)
