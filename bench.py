@@ -7,10 +7,20 @@ workload is 32 replicas x 4000 LJ atoms (rho 0.8442, geometric ladder
 T = 0.7 .. 2.0, r_c 2.5, skin 0.3, dt 0.005, N_x 50), batched mixed
 precision; the plain per-replica FP64 form is timed beside it.
 
+The input is prepared untimed: every replica is melted at T = 1.5 from the
+FCC start, then equilibrated at its ladder temperature, so that the timed
+window sees liquid-state list-update rates that differ along the ladder.
+The timed window is placed so that an exchange attempt falls in its middle
+(at the workload's N_x = 50 a 20-step window holds one attempt, a longer
+one one per 50 steps); the cost of one attempt is measured apart, from
+windows of N_x - 1 steps with and without one.
+
 Prints one JSON line: the metric and its value, the configuration, the
-dominant kernel's roofline figures, the CPU oracle's throughput and the
-oracle-checked tolerance of the same run, the plain FP64 form's throughput
-and the throughput under stochastic velocity rescaling.
+dominant kernel's roofline figures, the CPU oracle's throughput, the
+oracle-checked tolerance of the same configuration (on seeded injected
+states), the plain per-replica FP64 form's throughput (the ratio's
+baseline), the batched FP64 form's (the precision effect alone), and the
+throughput under stochastic velocity rescaling.
 """
 from __future__ import annotations
 
@@ -87,6 +97,30 @@ def progress(msg):
     print("bench: " + msg, file=sys.stderr, flush=True)
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def melted_states(R, W, cfg, N, rho, T, melt_steps, kw):
+    """Untimed input preparation: every replica melted at T = 1.5 (a flat
+    ladder 1.5 (1 + 1e-9 k), so that all replicas are thermostatted at the
+    melting temperature) from the FCC start; returns the states (x, v) in
+    atom-id order."""
+    Tm = 1.5 * (1.0 + 1e-9 * np.arange(len(N)))
+    em = R.Engine(N, Tm, 0.0, cfg["rc"], cfg["skin"], cfg["dt"], 10**9, cfg["seed"] + 1000, **kw)
+    em.step(melt_steps)
+    st = [em.get_state(r) for r in range(len(N))]
+    em.close()
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -94,9 +128,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="lj-32x4000")
     ap.add_argument("--engine", default=None, help="persistent | lockstep (default: autotuned)")
+    ap.add_argument("--melt-steps", type=int, default=500,
+                    help="input preparation: steps at T = 1.5 from the FCC start (0: start from FCC)")
+    ap.add_argument("--equil-steps", type=int, default=500,
+                    help="input preparation: steps at the ladder after melting")
     ap.add_argument("--plain-steps", type=int, default=100)
+    ap.add_argument("--fp64-steps", type=int, default=1000,
+                    help="steps of the batched FP64 form (the precision effect alone; 0: skip)")
     ap.add_argument("--svr-steps", type=int, default=1000,
                     help="steps of the same workload under stochastic velocity rescaling (0: skip)")
+    ap.add_argument("--attempt-reps", type=int, default=10,
+                    help="windows with and without an exchange attempt, for the per-attempt cost")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -122,6 +164,7 @@ def main():
     N, rho, T = cfg["N_list"], cfg["rho_list"], cfg["T_list"]
     rc, skin, dt, Nx, seed = cfg["rc"], cfg["skin"], cfg["dt"], cfg["Nx"], cfg["seed"]
     atoms = int(N.sum())
+    Rn = len(N)
     kw = dict(rho_per_replica=rho, gamma=cfg["gamma"])
     tune = {}
     if args.engine:
@@ -134,46 +177,81 @@ def main():
         os.makedirs(os.path.dirname(tune["tune_cache"]), exist_ok=True)
 
     # ---- batched mixed-precision form ------------------------------------
-    progress("%s: %d replicas, %d atoms; creating the context" % (args.workload, len(N), atoms))
+    progress("%s: %d replicas, %d atoms; creating the context" % (args.workload, Rn, atoms))
     eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune)
     engine_used, tpa_used, team_used = eng.query_config()
+    start = "FCC lattice, Maxwell-Boltzmann velocities at the ladder"
+    if args.melt_steps > 0:
+        progress("input preparation: %d steps at T = 1.5, then %d at the ladder" % (args.melt_steps,
+                                                                                  args.equil_steps))
+        for r, (x, v) in enumerate(melted_states(R, W, cfg, N, rho, T, args.melt_steps, kw)):
+            eng.set_state(r, x, v)
+        start = "melted: %d steps at T = 1.5 from FCC, then %d at the ladder (untimed)" % (args.melt_steps,
+                                                                                       args.equil_steps)
+    eng.step(args.equil_steps if args.melt_steps > 0 else 0)
+    prepared = [eng.get_state(r) for r in range(Rn)] if (args.plain_steps or args.fp64_steps) else None
     progress("engine %s, %d lanes per atom; %d warm-up steps" % (engine_used, tpa_used, args.warmup))
     eng.step(args.warmup)
+    # the timed window holds an exchange attempt: its middle step is a
+    # multiple of N_x (untimed padding steps before it)
+    s_now = int(eng.query_steps()[0][0])
+    pad = (-(s_now + (args.steps + 1) // 2)) % Nx
+    eng.step(pad)
     steps0, reb0 = eng.query_steps()
+    att0, acc0 = eng.query_acceptance()
     torch.cuda.synchronize()
     eng.profile(1)
     t0 = time.perf_counter()
-    eng.step(args.steps)
-    eng.query_energies()  # synchronises the library stream
+    eng.step(args.steps)  # (returns after synchronising the library's stream)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     eng.profile(0)
     k_ms, k_n = eng.query_kernel_time()
     steps1, reb1 = eng.query_steps()
+    att1, acc1 = eng.query_acceptance()
     done = int(((steps1 - steps0) * N).sum())
     value = done / (t1 - t0)
     ms_per_step = 1e3 * (t1 - t0) / args.steps
-    acc_att, acc_acc = eng.query_acceptance()
+    win_att = int((att1 - att0).sum())
+    win_acc = int((acc1 - acc0).sum())
+    progress("%d timed steps: %.4f ms per step, %d exchange records in the window" % (args.steps, ms_per_step,
+                                                                                   win_att))
 
-    progress("%d timed steps: %.4f ms per step; counting pairs" % (args.steps, ms_per_step))
-    # state and forces of two replicas, for the tolerance check of the CPU
-    # leg, and their pair counts (the algorithmic work)
+    # ---- cost of one exchange attempt: windows of N_x - 1 steps with no
+    # attempt (starting at a multiple of N_x) against the same windows with
+    # one attempt in their middle (untimed steps realign between them)
+    attempt = None
+    if args.attempt_reps > 0 and Nx >= 3:
+        tA, tB = [], []
+        for rep in range(args.attempt_reps):
+            for kind in ("A", "B"):
+                s_now = int(eng.query_steps()[0][0])
+                phase = 0 if kind == "A" else Nx // 2
+                eng.step((phase - s_now) % Nx)
+                torch.cuda.synchronize()
+                a = time.perf_counter()
+                eng.step(Nx - 1)
+                torch.cuda.synchronize()
+                (tA if kind == "A" else tB).append(time.perf_counter() - a)
+        attempt = {"per_attempt_us": 1e6 * (np.mean(tB) - np.mean(tA)),
+                   "window_steps": Nx - 1, "windows_each": args.attempt_reps,
+                   "ms_per_step_no_attempt": 1e3 * np.mean(tA) / (Nx - 1),
+                   "ms_per_step_one_attempt": 1e3 * np.mean(tB) / (Nx - 1)}
+
+    progress("counting pairs")
     L = eng.query_box()
-    snaps, counts = [], []
-    for r in (0, len(N) - 1):
+    # pair counts of two replicas at the states the run reached, for the
+    # algorithmic flops (27 per unique in-cutoff pair, 9 per unique pair in
+    # the skin shell); the persistent kernel does the whole timed run in
+    # one launch, the lockstep engine's fused force kernel one step
+    counts = []
+    for r in (0, Rn - 1):
         x, _ = eng.get_state(r)
-        F, U = eng.compute_forces(r)
-        snaps.append((r, x, F, U))
         counts.append(pair_counts(x, L[r], rc, rc + skin) + (int(N[r]),))
-
-    # algorithmic flops per atom-step: 27 per unique in-cutoff pair and 9 per
-    # unique pair in the skin shell (measured pair counts of two replicas).
-    # The lockstep engine's dominant kernel does one step of every replica
-    # per launch; the persistent kernel does the whole timed run.
-    flop_per_atom = np.mean([(27 * c + 9 * s) / n for c, s, n in counts])
-    flops_launch = flop_per_atom * (atoms if engine_used == "lockstep" else done / max(1, k_n))
-    achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+    flop_per_atom = np.mean([(27 * c + 9 * sk) / n for c, sk, n in counts])
     atom_steps_launch = atoms if engine_used == "lockstep" else done / max(1, k_n)
+    flops_launch = flop_per_atom * atom_steps_launch
+    achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
     tr = TRAFFIC.get((args.workload, engine_used, tpa_used))
     src = kernel_source_hash()
     traffic = None
@@ -187,56 +265,77 @@ def main():
                 "frac_unpacked": (achieved / PEAK_FP32_UNPACKED_TFLOPS) if achieved else None,
                 "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed,%d,false>" % tpa_used,
                 "kernel_ms": k_ms, "launches_timed": k_n, "atom_steps_per_launch": atom_steps_launch,
-                "flop_per_atom_step": float(flop_per_atom), "kernel_src": src}
-    eng.close()
+                "flop_per_atom_step": float(flop_per_atom), "kernel_src": src,
+                "wall_over_kernel": ((t1 - t0) * 1e3 / (k_ms * k_n)) if (engine_used != "lockstep" and k_ms > 0)
+                else None}
 
-    # ---- plain per-replica FP64 form ---------------------------------------
-    plain = None
-    if args.plain_steps > 0:
-        ep = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="fp64", form="plain", **kw)
-        ep.step(min(args.plain_steps, 50))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ep.step(args.plain_steps)
-        ep.query_energies()
-        t1 = time.perf_counter()
-        pv = atoms * args.plain_steps / (t1 - t0)
-        plain = {"value": pv, "unit": "atom-steps/s", "ms_per_step": 1e3 * (t1 - t0) / args.plain_steps,
-                 "steps": args.plain_steps, "ratio_mixed_over_plain": value / pv}
-        ep.close()
-
-    # ---- the paper's thermostat (stochastic velocity rescaling) ------------
-    svr = None
-    if args.svr_steps > 0:
-        es = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", thermostat="svr",
-                      engine=engine_used, threads_per_atom=tpa_used, **kw)
-        es.step(min(args.svr_steps, 100))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        es.step(args.svr_steps)
-        es.query_energies()
-        t1 = time.perf_counter()
-        svr = {"value": atoms * args.svr_steps / (t1 - t0), "unit": "atom-steps/s", "steps": args.svr_steps,
-               "ms_per_step": 1e3 * (t1 - t0) / args.svr_steps}
-        es.close()
-
-    # ---- CPU leg: the oracle, (1) checking the GPU's forces and energy on the
-    # states taken above, (2) timed on a bounded sample of the workload ----
-    cpu = None
+    # ---- tolerance of the same configuration against the oracle, on
+    # seeded injected states (perturbed FCC on the position grid,
+    # FP32-representable velocities): forces of every atom (or of 64 sampled
+    # atoms of replicas too large for the all-pairs oracle) and the energy
     tol = None
     if not args.no_cpu:
         import oracle
-        tol = {"force_normwise_max": 0.0, "energy_rel_max": 0.0}
-        for r, x, F, U in snaps:
-            g = np.random.default_rng(r)
-            idx = g.choice(int(N[r]), size=min(64, int(N[r])), replace=False)
-            Fo = np.array([oracle.force_on(x, L[r], rc, int(i))[0] for i in idx])
-            rms = np.sqrt((Fo * Fo).sum(1).mean())
-            tol["force_normwise_max"] = max(tol["force_normwise_max"], float(np.abs(F[idx] - Fo).max() / rms))
-            if r == 0:
-                _, Uo, _ = oracle.forces(x, L[r], rc)
-                tol["energy_rel_max"] = abs(U - Uo) / abs(Uo)
+        tol = {"force_normwise_max": 0.0, "energy_rel_max": 0.0, "input": "seeded perturbed FCC (amp 0.07)"}
+        for r in (0, Rn - 1):
+            x = W.perturbed_fcc(int(N[r]), L[r], 0.07, 7000 + r)
+            eng.set_state(r, x, W.maxwell(int(N[r]), float(T[r]), 7100 + r))
+            F, U = eng.compute_forces(r)
+            if N[r] <= 20000:
+                Fo, Uo, _ = oracle.forces(x, L[r], rc)
+                tol["energy_rel_max"] = max(tol["energy_rel_max"], abs(U - Uo) / abs(Uo))
+                rms = np.sqrt((Fo * Fo).sum(1).mean())
+                tol["force_normwise_max"] = max(tol["force_normwise_max"], float(np.abs(F - Fo).max() / rms))
+            else:
+                g = np.random.default_rng(r)
+                idx = g.choice(int(N[r]), size=64, replace=False)
+                Fo = np.array([oracle.force_on(x, L[r], rc, int(i))[0] for i in idx])
+                rms = np.sqrt((Fo * Fo).sum(1).mean())
+                tol["force_normwise_max"] = max(tol["force_normwise_max"],
+                                                float(np.abs(F[idx] - Fo).max() / rms))
+                tol["energy"] = "not checked above 20000 atoms per replica (all-pairs oracle)"
         tol["passed"] = bool(tol["force_normwise_max"] <= 1e-5 and tol["energy_rel_max"] <= 1e-5)
+    eng.close()
+
+    def other_form(label, steps, **opts):
+        """Throughput of another form of the same workload from the same
+        prepared states (untimed warm-up of min(steps, 50) steps)."""
+        e = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, **kw, **opts)
+        if prepared is not None:
+            for r, (x, v) in enumerate(prepared):
+                e.set_state(r, x, v)
+        e.step(min(steps, 50))
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        e.step(steps)
+        torch.cuda.synchronize()
+        b = time.perf_counter()
+        out = {"value": atoms * steps / (b - a), "unit": "atom-steps/s", "steps": steps,
+               "ms_per_step": 1e3 * (b - a) / steps, "config": e.query_config()}
+        e.close()
+        progress("%s: %.4f ms per step" % (label, out["ms_per_step"]))
+        return out
+
+    # ---- the precision effect alone: batched FP64 (autotuned the same way)
+    fp64 = None
+    if args.fp64_steps > 0:
+        fp64 = other_form("batched fp64", args.fp64_steps, precision="fp64", form="batched", **tune)
+        fp64["ratio_mixed_over_fp64"] = value / fp64["value"]
+    # ---- plain per-replica FP64 form (the baseline the ratio is quoted on)
+    plain = None
+    if args.plain_steps > 0:
+        plain = other_form("plain fp64", args.plain_steps, precision="fp64", form="plain")
+        plain["ratio_mixed_over_plain"] = value / plain["value"]
+    # ---- the paper's thermostat (stochastic velocity rescaling) ------------
+    svr = None
+    if args.svr_steps > 0:
+        svr = other_form("mixed, velocity rescale", args.svr_steps, precision="mixed", form="batched",
+                         thermostat="svr", engine=engine_used, threads_per_atom=tpa_used)
+
+    # ---- CPU leg: the oracle timed on a bounded sample of the workload ----
+    cpu = None
+    if not args.no_cpu:
+        import oracle
         nthreads = oracle.num_threads()
         ens = oracle.Ensemble(N, L, T, rc, skin, dt, cfg["gamma"], seed)
         t0 = time.perf_counter()
@@ -245,25 +344,27 @@ def main():
         n_more = max(1, int(args.cpu_seconds / max(t_probe / 2, 1e-6)))
         t0 = time.perf_counter()
         ens.run_sync(n_more, 10**9)
-        t1 = time.perf_counter()
-        cpu = {"value": atoms * n_more / (t1 - t0), "unit": "atom-steps/s", "cores": nthreads, "kind": "oracle",
+        t1c = time.perf_counter()
+        cpu = {"value": atoms * n_more / (t1c - t0), "unit": "atom-steps/s", "cores": nthreads, "kind": "oracle",
+               "cpu_model": cpu_model(),
                "sample": "%d steps of all %d replicas of %s from the FCC start (Verlet-list oracle, "
-                         "OpenMP over replicas)" % (n_more, len(N), args.workload)}
+                         "OpenMP over replicas, %d threads)" % (n_more, Rn, args.workload, nthreads)}
 
     out = {"metric": METRIC, "value": value, "unit": "atom-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": args.workload, "replicas": int(len(N)), "atoms": atoms,
+           "config": {"workload": args.workload, "replicas": int(Rn), "atoms": atoms,
                       "atoms_per_replica": int(N[0]) if len(set(N.tolist())) == 1 else "uneven",
                       "rho": float(rho[0]) if len(set(rho.tolist())) == 1 else "uneven",
                       "T_ladder": [float(T[0]), float(T[-1])], "r_c": rc, "skin": skin, "dt": dt, "N_x": Nx,
+                      "start": start, "exchange": "synchronous",
                       "precision": "FP32 pair arithmetic, 32-bit fixed-point positions, FP64 energies/exchange",
                       "engine": engine_used, "threads_per_atom": tpa_used, "team_size": team_used,
                       "tuning": "explicit" if args.engine else "autotuned",
                       "parallelism": "replicas batched on 1 GPU"},
-           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "thermostat_svr": svr,
-           "tolerance": tol,
-           "exchange": {"attempts": int(acc_att.sum()), "accepted": int(acc_acc.sum())},
+           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "batched_fp64": fp64,
+           "thermostat_svr": svr, "tolerance": tol,
+           "exchange": {"records_in_window": win_att, "accepted_in_window": win_acc, "attempt_cost": attempt},
            "rebuilds_per_replica_step": float((reb1 - reb0).sum() / max(1, (steps1 - steps0).sum()))}
     print(json.dumps(out))
 

@@ -60,7 +60,17 @@ extern "C" {
 #define RE_BATCHED 0    /* all replicas advanced together on the device */
 #define RE_PLAIN 1      /* one sequence of kernel launches per replica per step */
 #define RE_LOCKSTEP 0   /* batched: one launch sequence per step for all replicas */
-#define RE_PERSISTENT 1 /* batched: one persistent launch per re_step call */
+#define RE_PERSISTENT 1 /* batched: one persistent launch per re_step call.  The
+                           workgroups serving one replica wait for each other
+                           (team barriers, exchange partners), so every
+                           workgroup of the launch must be resident at once:
+                           the engine sizes its grid to the resident capacity
+                           of the device (one 1024-thread workgroup per CU)
+                           and assumes it has the GPU to itself.  Kernels of
+                           other processes or streams that occupy CUs during
+                           a call can keep a team from becoming resident; the
+                           watchdog then ends the call with RE_ETIMEOUT
+                           instead of hanging. */
 /* exchange timing */
 #define RE_SYNC 0  /* attempt after every N_x steps of every replica */
 #define RE_ASYNC 1 /* rotating master triggers after N_x of its own steps */
@@ -84,7 +94,9 @@ typedef struct {
     void* stream;                /* hipStream_t to run on; NULL: a library stream  */
     double watchdog_seconds;     /* bound on every device-side wait; 0: 10 s       */
     int64_t log_capacity;        /* exchange records kept (ring); 0: 1 << 18       */
-    int threads_per_atom;        /* force-kernel lanes per atom; 0: autotuned      */
+    int threads_per_atom;        /* force-kernel lanes per atom (1, 2, 4 or 8);
+                                    0: 4, or the autotuner's choice when
+                                    autotune is set                        */
     int block_size;              /* threads per block of the wide kernels; 0: auto */
     int team_size;               /* persistent engine: workgroups per replica; 0: auto */
     const char* tune_cache;      /* autotuner JSON cache path; NULL: no cache file */
@@ -216,6 +228,14 @@ int re_set_state(re_ctx* ctx, int r, const double* x, const double* v);
 /* Forces (3N doubles, atom-id order) and potential energy of replica r at its
  * current positions; changes no state.  Either output may be NULL. */
 int re_compute_forces(re_ctx* ctx, int r, double* F, double* U);
+
+/* Forces (3N doubles, atom-id order) on replica r at its current step
+ * boundary as the engine that ran last computed them: the final force phase
+ * of the last re_step (the persistent kernel's own force pass when that
+ * engine runs), or the list update after re_create / re_set_state.  Truncated
+ * and shifted LJ at cutoff r_c (Example section).  Reads no positions and
+ * recomputes nothing.  Errors: RE_EINVAL (bad r or NULL F). */
+int re_query_forces(re_ctx* ctx, int r, double* F);
 
 /* Asynchronous mode only, for testing: fix the join steps of the next A
  * attempts instead of letting device timing decide.  join is A x R (row a:

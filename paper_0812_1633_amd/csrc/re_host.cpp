@@ -66,7 +66,13 @@ struct re_ctx {
     std::string pers_why;        // why not, when it does not
     PersistState ps{};
     CallParams* d_call = nullptr;
-    int64_t* d_target = nullptr;
+    CallParams* h_call = nullptr;  // pinned staging of the per-call parameters
+    // status of a call, one contiguous block read back with one copy:
+    // error bits (u32), list overflow (u32), next attempt per replica (R x
+    // i64), steps per replica (R x i64); h_stat is its pinned host copy
+    unsigned char* d_stat = nullptr;
+    unsigned char* h_stat = nullptr;
+    std::vector<void*> pinned;     // pinned host allocations
     int64_t* d_sched = nullptr;
     int64_t sched_cap = 0;
     std::vector<int64_t> sched;  // pending injected schedule (A x R)
@@ -582,15 +588,16 @@ static int run_persistent(re_ctx* c, int64_t n)
 {
     if (!c->pers_ok) return fail(c, RE_ESTATE, "%s", c->pers_why.c_str());
     const int R = c->R;
-    std::vector<int64_t> steps(R);
-    int rc = d2h(c, steps.data(), c->d.steps, R);
-    if (rc) return rc;
-    CallParams cp{};
+    int rc;
+    // per-call parameters through pinned memory: the copy is queued and the
+    // host goes on; every call ends with a synchronisation, so the staging
+    // buffer is free again when the next call writes it
+    CallParams& cp = *c->h_call;
+    cp = CallParams{};
     cp.cur0 = c->cur;
     cp.k0 = c->next_attempt;
-    cp.target = c->d_target;
     cp.sched = c->d_sched;
-    std::vector<int64_t> tgt(R);
+    cp.apply_alpha = c->pending_alpha;
     if (!c->sched.empty()) {
         cp.mode = kModeSchedule;
         cp.A = c->sched_A;
@@ -600,22 +607,12 @@ static int run_persistent(re_ctx* c, int64_t n)
             cp.sched = c->d_sched;
         }
         HIPCHK(c, hipMemcpyAsync(c->d_sched, c->sched.data(), c->sched.size() * 8, hipMemcpyHostToDevice, c->stream));
-        for (int r = 0; r < R; ++r) tgt[r] = c->sched[(size_t)(c->sched_A - 1) * R + r];
     } else {
         cp.mode = c->xmode == RE_ASYNC ? kModeAsync : kModeSync;
-        cp.A = 0;
-        for (int r = 0; r < R; ++r) tgt[r] = steps[r] + n;
+        cp.n = n;
     }
-    HIPCHK(c, hipMemcpyAsync(c->d_target, tgt.data(), R * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_call, &cp, sizeof cp, hipMemcpyHostToDevice, c->stream));
-    if (c->pending_alpha) {
-        // a factor set outside the persistent engine (re_exchange) is applied
-        // by its first step
-        const std::vector<int32_t> ones(R, 1);
-        HIPCHK(c, hipMemcpyAsync(c->ps.apend, ones.data(), R * 4, hipMemcpyHostToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        c->pending_alpha = 0;
-    }
+    HIPCHK(c, hipMemcpyAsync(c->d_call, c->h_call, sizeof(CallParams), hipMemcpyHostToDevice, c->stream));
+    c->pending_alpha = 0;
     const bool f64 = c->prec == RE_FP64;
     if (!c->gexec) {
         const PersistArgs pa = persist_args(c);
@@ -642,19 +639,23 @@ static int run_persistent(re_ctx* c, int64_t n)
         HIPCHK(c, hipEventRecord(c->ev[c->ev_used + 1], c->stream));
         c->ev_used += 2;
     }
-    uint32_t err = 0;
-    HIPCHK(c, hipMemcpyAsync(&err, c->ps.err, 4, hipMemcpyDeviceToHost, c->stream));
+    // error bits, overflow flag, next attempts and step counts: one copy, one
+    // synchronisation
+    HIPCHK(c, hipMemcpyAsync(c->h_stat, c->d_stat, 8 + 16 * (size_t)R, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    std::vector<int64_t> katt(R);
-    if ((rc = d2h(c, katt.data(), c->ps.katt, R))) return rc;
-    c->next_attempt = *std::max_element(katt.begin(), katt.end());
-    if ((rc = d2h(c, steps.data(), c->d.steps, R))) return rc;
+    uint32_t err = 0, ov = 0;
+    std::memcpy(&err, c->h_stat, 4);
+    std::memcpy(&ov, c->h_stat + 4, 4);
+    const int64_t* katt = reinterpret_cast<const int64_t*>(c->h_stat + 8);
+    const int64_t* steps = katt + R;
+    c->next_attempt = *std::max_element(katt, katt + R);
     c->step = steps[0];
     c->sched.clear();
     c->sched_A = 0;
     if (err & kErrTimeout)
         return fail(c, RE_ETIMEOUT, "a device-side wait made no progress for %.1f s; the run was aborted", c->watchdog);
-    return check_overflow(c);
+    if (ov) return fail(c, RE_EOVERFLOW, "a neighbour list exceeded its capacity of %d entries per atom", c->cfg.M);
+    return 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -893,12 +894,16 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.U, R);
     ALLOC(d.flag, 2 * R);
     ALLOC(d.rebuilds, R);
-    ALLOC(d.steps, R);
     ALLOC(d.attempts, R);
     ALLOC(d.accepts, R);
     ALLOC(d.log, c->cfg.log_cap);
     ALLOC(d.log_count, 1);
-    ALLOC(d.overflow, 1);
+    // the status block: error bits, overflow flag, next attempts, step counts
+    ALLOC(c->d_stat, 8 + 16 * (size_t)R);
+    c->ps.err = reinterpret_cast<uint32_t*>(c->d_stat);
+    d.overflow = reinterpret_cast<uint32_t*>(c->d_stat + 4);
+    c->ps.katt = reinterpret_cast<int64_t*>(c->d_stat + 8);
+    d.steps = c->ps.katt + R;
     ALLOC(d.fq, 4 * slots);
     ALLOC(d.wtab, 4 * (size_t)R + 4);
     if (c->thermo == kThermoSVR) ALLOC(d.svrq, slots);
@@ -907,7 +912,6 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(c->ps.upost, 2 * R);
     ALLOC(c->ps.spost, 2 * R);
     ALLOC(c->ps.apend, R);
-    ALLOC(c->ps.katt, R);
     ALLOC(c->ps.jprev, R);
     ALLOC(c->ps.ctl, 2 * R);
     ALLOC(c->ps.xdone, 1);
@@ -916,11 +920,21 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(c->ps.reach, 1);
     ALLOC(c->ps.beat, 1);
     ALLOC(c->ps.abort, 1);
-    ALLOC(c->ps.err, 1);
     ALLOC(c->ps.xmask, R);
     ALLOC(c->d_call, 1);
-    ALLOC(c->d_target, R);
 #undef ALLOC
+    {
+        void* h1 = nullptr;
+        void* h2 = nullptr;
+        if (hipHostMalloc(&h1, sizeof(CallParams), hipHostMallocDefault) != hipSuccess ||
+            (c->pinned.push_back(h1), hipHostMalloc(&h2, 8 + 16 * (size_t)R, hipHostMallocDefault) != hipSuccess)) {
+            c->err = "hipHostMalloc of the call staging failed";
+            return bail(RE_ENOMEM);
+        }
+        c->pinned.push_back(h2);
+        c->h_call = static_cast<CallParams*>(h1);
+        c->h_stat = static_cast<unsigned char*>(h2);
+    }
     if ((rc = build_tables(c))) return bail(rc);
 
     // per-replica constants and bookkeeping
@@ -1176,6 +1190,39 @@ int re_compute_forces(re_ctx* c, int r, double* F, double* U)
     return RE_OK;
 }
 
+int re_query_forces(re_ctx* c, int r, double* F)
+{
+    if (!c || r < 0 || r >= c->R || !F) return fail(c, RE_EINVAL, "bad arguments");
+    const RepDev& rd = c->rep[r];
+    const int N = rd.N;
+    int rc;
+    if (c->prec == RE_MIXED) {
+        std::vector<int4> p(N);
+        std::vector<float4> f(N);
+        if ((rc = d2h(c, p.data(), c->d.posi[c->cur] + rd.base, N))) return rc;
+        if ((rc = d2h(c, f.data(), c->d.frcf + rd.base, N))) return rc;
+        for (int k = 0; k < N; ++k) {
+            const int i = p[k].w;
+            if (i < 0 || i >= N) return fail(c, RE_EDEVICE, "corrupt atom id %d", i);
+            F[3 * i] = f[k].x;
+            F[3 * i + 1] = f[k].y;
+            F[3 * i + 2] = f[k].z;
+        }
+    } else {
+        std::vector<double4> p(N), f(N);
+        if ((rc = d2h(c, p.data(), c->d.posd[c->cur] + rd.base, N))) return rc;
+        if ((rc = d2h(c, f.data(), c->d.frcd + rd.base, N))) return rc;
+        for (int k = 0; k < N; ++k) {
+            const int i = (int)p[k].w;
+            if (i < 0 || i >= N) return fail(c, RE_EDEVICE, "corrupt atom id %d", i);
+            F[3 * i] = f[k].x;
+            F[3 * i + 1] = f[k].y;
+            F[3 * i + 2] = f[k].z;
+        }
+    }
+    return RE_OK;
+}
+
 int re_query_config(re_ctx* c, int* engine, int* threads_per_atom, int* team_size)
 {
     if (!c) return fail(nullptr, RE_EINVAL, "ctx is NULL");
@@ -1323,6 +1370,7 @@ void re_destroy(re_ctx* c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     for (void* p : c->allocs) (void)hipFree(p);
+    for (void* p : c->pinned) (void)hipHostFree(p);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -350,7 +350,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     int64_t knext = ps.katt[r];
     int64_t jprev = ps.jprev[r];
     int64_t asched = 0;  // next scheduled attempt (schedule mode)
-    int64_t target = cp.mode == kModeSchedule ? 0 : cp.target[r];
+    int64_t target = cp.mode == kModeSchedule ? 0 : s + cp.n;
     bool join_pending = false;
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
@@ -719,6 +719,7 @@ __global__ void k_persist_prepare(DevState d, PersistArgs pa, int nteams)
     if (i < R) {
         ps.slotbuf[(size_t)(cp.k0 & 1) * R + i] = d.slot[i];
         ps.katt[i] = cp.k0;
+        if (cp.apply_alpha) ps.apend[i] = 1;
     }
     if (i < 64 * nteams) pa.bar[i] = 0u;
     if (i < nteams) ps.xmask[i] = 0u;

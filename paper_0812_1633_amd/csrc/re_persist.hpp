@@ -33,8 +33,12 @@ struct PersistState {
 struct CallParams {
     int mode;             // kModeSync | kModeAsync | kModeSchedule
     int cur0;             // position buffer holding the current positions
+    int apply_alpha;      // nonzero: every replica's pending velocity factor (set
+                          // outside the engine, e.g. by re_exchange) is applied by
+                          // its first step
     int64_t k0;           // first attempt index of the call
-    const int64_t* target;// R: steps at which each replica stops (sync/async)
+    int64_t n;            // sync/async: steps each replica advances (its target is
+                          // its step count at the call's start plus n)
     const int64_t* sched; // A x R join steps (schedule mode)
     int64_t A;
 };

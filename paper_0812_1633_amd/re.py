@@ -76,6 +76,7 @@ def lib():
         L.re_get_state.argtypes = [vp, C.c_int, vp, vp]
         L.re_set_state.argtypes = [vp, C.c_int, vp, vp]
         L.re_compute_forces.argtypes = [vp, C.c_int, vp, vp]
+        L.re_query_forces.argtypes = [vp, C.c_int, vp]
         L.re_set_schedule.argtypes = [vp, vp, i64]
         L.re_test_exchange.argtypes = [vp, vp, vp, C.c_int, u64, i64, C.c_int, vp]
         L.re_test_philox.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int, vp]
@@ -91,7 +92,8 @@ def lib():
                   "re_query_slots", "re_query_box", "re_query_acceptance", "re_query_steps",
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
-                  "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count"):
+                  "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count",
+                  "re_query_forces"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -282,6 +284,14 @@ class Engine:
         if x.size != 3 * self._n(r) or v.size != 3 * self._n(r):
             raise ReError(RE_EINVAL, "x and v need 3 N values for replica %d" % r)
         _check(lib().re_set_state(self._ctx, int(r), _ptr(x), _ptr(v)), self._ctx)
+
+    def query_forces(self, r):
+        """Forces at the current boundary as the last engine pass computed
+        them (atom-id order)."""
+        n = self._n(r)
+        F = np.zeros((n, 3))
+        _check(lib().re_query_forces(self._ctx, int(r), _ptr(F)), self._ctx)
+        return F
 
     def compute_forces(self, r):
         n = self._n(r)

@@ -5,9 +5,10 @@ exchange statistics.
   synchronous form's observed stride equals N_x exactly, the asynchronous
   one's is at least 1, lambda and D are finite and positive;
 * acceptance rates of a long synchronous run (mixed precision on the GPU)
-  agree with the FP64 oracle's within 3 sigma overall and 4 sigma per ladder
-  pair (block-averaged errors; the trajectories themselves diverge
-  chaotically, so only statistics can agree), for both thermostats.
+  agree with the FP64 oracle's within 3 sigma overall and per ladder pair,
+  over more than 10^4 attempts per pair (block-averaged errors; the
+  trajectories themselves diverge chaotically, so only statistics can
+  agree), for both thermostats.
 """
 import numpy as np
 import pytest
@@ -69,7 +70,7 @@ def test_diffusion_driver(relib):
         assert r["attempts"] > 100
 
 
-def block_err(x, nblocks=20):
+def block_err(x, nblocks=40):
     x = np.asarray(x, np.float64)
     n = x.size // nblocks * nblocks
     b = x[:n].reshape(nblocks, -1).mean(1)
@@ -78,17 +79,29 @@ def block_err(x, nblocks=20):
 
 @pytest.mark.parametrize("thermostat", ["langevin", "svr"])
 def test_acceptance_matches_oracle(relib, thermostat):
-    R, N, Nx, steps, burn = 4, 256, 10, 16000, 1600
+    """Long-run acceptance, per ladder pair and overall, within 3 sigma of
+    the FP64 oracle's independent run (sigma from 40 block averages of
+    each run's 0/1 decisions, combined in quadrature), over more than 10^4
+    attempts per pair: 4 replicas x 256 atoms, attempts every step."""
+    import threading
+    R, N, Nx, steps, burn = 4, 256, 1, 23000, 1000
     T = W.ladder(0.8, 1.0, R)
     rc, skin, dt, rho, seed = 2.5, 0.3, 0.005, 0.8442, 17
-    e = relib.Engine([N] * R, T, rho, rc, skin, dt, Nx, seed, thermostat=thermostat, engine="persistent",
-                     log_capacity=1 << 16, watchdog_seconds=10)
-    L = e.query_box()[0]
-    e.step(steps)
-    glog, _ = e.query_exchange_log()
-    e.close()
+    L = oracle.box_length(N, rho)
     ens = oracle.Ensemble([N] * R, [L] * R, T, rc, skin, dt, 1.0, seed + 1, thermostat=thermostat)
-    ens.run_sync(steps, Nx)
+    # the oracle's run (C, outside the interpreter lock) beside the GPU's
+    th = threading.Thread(target=ens.run_sync, args=(steps, Nx))
+    th.start()
+    try:
+        e = relib.Engine([N] * R, T, rho, rc, skin, dt, Nx, seed, thermostat=thermostat, engine="persistent",
+                         log_capacity=1 << 17, watchdog_seconds=10)
+        assert e.query_box()[0] == L
+        e.step(steps)
+        glog, total = e.query_exchange_log(cap=1 << 17)
+        assert total == len(glog)
+        e.close()
+    finally:
+        th.join()
     kmin = burn // Nx
 
     def per_pair(log):
@@ -105,5 +118,6 @@ def test_acceptance_matches_oracle(relib, thermostat):
     assert 0.05 < allo.mean() < 0.95  # the ladder gives informative acceptance
     assert abs(allg.mean() - allo.mean()) <= 3 * s, (allg.mean(), allo.mean(), s)
     for j in range(R - 1):
+        assert len(pg[j]) >= 10**4 and len(po[j]) >= 10**4, (j, len(pg[j]), len(po[j]))
         sj = np.sqrt(block_err(pg[j]) ** 2 + block_err(po[j]) ** 2)
-        assert abs(np.mean(pg[j]) - np.mean(po[j])) <= 4 * sj, (j, np.mean(pg[j]), np.mean(po[j]), sj)
+        assert abs(np.mean(pg[j]) - np.mean(po[j])) <= 3 * sj, (j, np.mean(pg[j]), np.mean(po[j]), sj)

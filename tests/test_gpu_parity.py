@@ -384,23 +384,27 @@ def test_capped_cell_grid(relib, engine):
     """A replica large enough that the cell grid is capped at 32 cells per
     side (cells wider than half the list radius, more than 64 candidates per
     list-build lane, so the list build also takes its slow path): forces of
-    sampled atoms equal the oracle's after 30 steps, and the persistent and
-    lockstep engines agree bitwise."""
+    sampled atoms of an injected state equal the oracle's one-atom sums, and
+    after 30 steps the persistent and lockstep engines agree bitwise."""
     N, rho, T = 1000000, 0.8442, 1.0
     e = relib.Engine([N], [T], rho, RC, SKIN, DT, 10**6, 3, engine=engine, watchdog_seconds=10)
     L = e.query_box()[0]
     assert L / 32 > RC + SKIN  # the grid is capped: cells wider than the list radius
-    e.step(30)
-    x, v = e.get_state(0)
+    x0 = W.perturbed_fcc(N, L, 0.05, 17)
+    v0 = W.maxwell(N, T, 18)
+    e.set_state(0, x0, v0)
     F, U = e.compute_forces(0)
     g = np.random.default_rng(5)
     idx = g.choice(N, size=48, replace=False)
-    Fo = np.array([oracle.force_on(x, L, RC, int(i))[0] for i in idx])
+    Fo = np.array([oracle.force_on(x0, L, RC, int(i))[0] for i in idx])
     rms = np.sqrt((Fo * Fo).sum(1).mean())
     assert np.abs(F[idx] - Fo).max() / rms <= 1e-5
+    e.step(30)
+    x, v = e.get_state(0)
     e.close()
     if engine == "persistent":
         e2 = relib.Engine([N], [T], rho, RC, SKIN, DT, 10**6, 3, engine="lockstep")
+        e2.set_state(0, x0, v0)
         e2.step(30)
         x2, v2 = e2.get_state(0)
         assert np.array_equal(x, x2) and np.array_equal(v, v2)

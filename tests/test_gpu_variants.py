@@ -1,0 +1,223 @@
+"""GPU parity of every launch variant the library can run, against the FP64
+oracle.
+
+The autotuner may pick either batched engine and 1, 2, 4 or 8 force lanes
+per atom; each of these runs its own force pass (lane-group reduction, LDS
+or global neighbour positions, list build from LDS keys or from global
+memory).  Every combination is checked here against the oracle:
+
+* the engine's own force pass: one step from an injected state, then the
+  forces and energy the engine stored at the new boundary against the
+  oracle's forces at the oracle's own positions after the same step
+  (normwise 1e-5 mixed / 1e-12 FP64; positions agree to rounding);
+* 100-step trajectories (two calls), positions within 1e-4 (mixed) /
+  1e-9 (FP64) of the oracle's, energies within 1e-4 / 1e-10;
+* both at the headline parameters (r_c 2.5, skin 0.3, dt 0.005) and at the
+  largest ladder's (r_c 3.0, skin 0.4, dt 0.004, about 140 neighbours per
+  atom within the list radius, so list-build lanes often pass 64 candidates
+  and take their walk path);
+* the exact headline launch (32 x 4000 atoms, persistent engine, 2 lanes
+  per atom, teams of 8 workgroups), one step;
+* replicas of the largest ladder's full size (108000 atoms): sampled forces
+  against the oracle's one-atom sums, and the two engines bitwise equal.
+
+Inputs are seeded (paper_0812_1633_amd.workloads): perturbed FCC positions
+on the 32-bit grid and FP32-representable Maxwell-Boltzmann velocities,
+exact in both representations, so only arithmetic differs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_0812_1633_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+PARAMS = {"c2": (2.5, 0.3, 0.005), "c5": (3.0, 0.4, 0.004)}
+NOX = 10**9  # an exchange stride no run reaches
+
+
+@pytest.fixture(scope="module")
+def relib():
+    from paper_0812_1633_amd import re as R
+    R.lib()
+    return R
+
+
+def normwise(F, Fo):
+    return np.abs(F - Fo).max() / np.sqrt((Fo * Fo).sum(1).mean())
+
+
+def mi_dist(x, y, L):
+    d = x - y
+    d -= L * np.round(d / L)
+    return np.sqrt((d * d).sum(1)).max()
+
+
+def injected(eng, N, T, rho, amp, seed):
+    """Seeded start for every replica of eng; returns (L, x, v) lists."""
+    L = eng.query_box()
+    xs, vs = [], []
+    for r in range(len(N)):
+        assert L[r] == oracle.box_length(int(N[r]), rho)
+        x = W.perturbed_fcc(int(N[r]), L[r], amp, seed + r)
+        v = W.maxwell(int(N[r]), T[r], seed + 100 + r)
+        eng.set_state(r, x, v)
+        xs.append(x)
+        vs.append(v)
+    return L, xs, vs
+
+
+def oracle_ensemble(N, L, T, rc, skin, dt, seed, xs, vs, thermostat="langevin"):
+    return oracle.Ensemble(N, L, T, rc, skin, dt, 1.0, seed, thermostat=thermostat,
+                           x=np.concatenate([a.reshape(-1) for a in xs]),
+                           v=np.concatenate([a.reshape(-1) for a in vs]))
+
+
+def replica_F(ens, r):
+    a = ens.off[r]
+    return ens.F[a:a + 3 * ens.N[r]].reshape(-1, 3)
+
+
+VARIANTS = [(e, t) for e in ("lockstep", "persistent") for t in (1, 2, 4, 8)]
+FORMS = [("c2", "mixed"), ("c2", "fp64"), ("c5", "mixed")]
+
+
+@pytest.mark.parametrize("engine,tpa", VARIANTS)
+@pytest.mark.parametrize("params,precision", FORMS)
+def test_engine_force_pass(relib, engine, tpa, params, precision):
+    """One step, then the forces the engine's own force pass stored."""
+    rc, skin, dt = PARAMS[params]
+    N = [4000, 1777]  # (a ragged tail: 1777 is not a multiple of 64)
+    T = [0.9, 1.6]
+    rho, seed = 0.8442, 31
+    eng = relib.Engine(N, T, rho, rc, skin, dt, NOX, seed, precision=precision, engine=engine,
+                       threads_per_atom=tpa, watchdog_seconds=10)
+    assert eng.query_config()[:2] == (engine, tpa)
+    L, xs, vs = injected(eng, N, T, rho, 0.06, 500)
+    # the list update of set_state stores the forces its own pass computed;
+    # the query pass computes the same sums
+    for r in range(2):
+        Fq, _ = eng.compute_forces(r)
+        assert np.array_equal(eng.query_forces(r), Fq)
+    eng.step(1)
+    U = eng.query_energies()
+    ens = oracle_ensemble(N, L, T, rc, skin, dt, seed, xs, vs)
+    ens.run_sync(1, NOX)
+    tol = 1e-5 if precision == "mixed" else 1e-12
+    for r in range(2):
+        xg, _ = eng.get_state(r)
+        assert mi_dist(xg, ens.replica_x(r), L[r]) <= (1e-6 if precision == "mixed" else 1e-12)
+        F = eng.query_forces(r)
+        err = normwise(F, replica_F(ens, r))
+        assert err <= tol, (r, err)
+        assert abs(U[r] - ens.U[r]) <= tol * abs(ens.U[r]), (r, U[r], ens.U[r])
+    eng.close()
+
+
+@pytest.mark.parametrize("engine,tpa", VARIANTS)
+@pytest.mark.parametrize("params,precision", FORMS)
+def test_trajectory_every_variant(relib, engine, tpa, params, precision):
+    """100 steps in two calls (neither ends on an exchange step) from a
+    seeded state: positions and energies against the oracle's run."""
+    rc, skin, dt = PARAMS[params]
+    N = [2000, 1101]
+    T = [0.85, 1.5]
+    rho, seed = 0.8442, 7
+    eng = relib.Engine(N, T, rho, rc, skin, dt, NOX, seed, precision=precision, engine=engine,
+                       threads_per_atom=tpa, watchdog_seconds=10)
+    L, xs, vs = injected(eng, N, T, rho, 0.05, 900)
+    eng.step(37)
+    eng.step(63)
+    steps, reb = eng.query_steps()
+    assert list(steps) == [100, 100]
+    U = eng.query_energies()
+    ens = oracle_ensemble(N, L, T, rc, skin, dt, seed, xs, vs)
+    ens.run_sync(100, NOX)
+    for r in range(2):
+        xg, _ = eng.get_state(r)
+        d = mi_dist(xg, ens.replica_x(r), L[r])
+        assert d <= (1e-4 if precision == "mixed" else 1e-9), (r, d)
+        assert abs(U[r] - ens.U[r]) <= (1e-4 if precision == "mixed" else 1e-10) * abs(ens.U[r])
+        # list updates happened, of the oracle's order
+        assert reb[r] >= 2 and abs(int(reb[r]) - int(ens.rebuilds[r])) <= max(2, int(ens.rebuilds[r]) // 3)
+    eng.close()
+
+
+def test_headline_launch(relib):
+    """The headline workload's exact launch: 32 replicas x 4000 atoms on the
+    geometric ladder 0.7 .. 2.0, persistent engine, 2 lanes per atom, teams
+    of 8 workgroups.  One step from an injected state: every replica's
+    positions, forces (from the persistent kernel's own pass) and energy
+    against the oracle's."""
+    R, N = 32, 4000
+    rc, skin, dt = PARAMS["c2"]
+    T = W.ladder(0.7, 2.0, R)
+    rho, seed = 0.8442, 1
+    Ns = [N] * R
+    eng = relib.Engine(Ns, T, rho, rc, skin, dt, NOX, seed, engine="persistent", threads_per_atom=2,
+                       team_size=8, watchdog_seconds=10)
+    assert eng.query_config() == ("persistent", 2, 8)
+    L, xs, vs = injected(eng, Ns, T, rho, 0.05, 2000)
+    eng.step(1)
+    U = eng.query_energies()
+    ens = oracle_ensemble(Ns, L, T, rc, skin, dt, seed, xs, vs)
+    ens.run_sync(1, NOX)
+    for r in range(R):
+        xg, _ = eng.get_state(r)
+        assert mi_dist(xg, ens.replica_x(r), L[r]) <= 1e-6, r
+        assert normwise(eng.query_forces(r), replica_F(ens, r)) <= 1e-5, r
+        assert abs(U[r] - ens.U[r]) <= 1e-5 * abs(ens.U[r]), r
+    eng.close()
+
+
+@pytest.mark.parametrize("engine", ["lockstep", "persistent"])
+def test_largest_ladder_replica_size(relib, engine):
+    """Two replicas of the largest ladder's size (108000 atoms, r_c 3.0,
+    skin 0.4, dt 0.004, ladder ends 0.7 and 3.5): forces of sampled atoms of
+    an injected state against the oracle's one-atom sums, in the lane count
+    the context runs; then 20 steps, bitwise equal in both engines."""
+    N, rho = 108000, 0.8442
+    rc, skin, dt = PARAMS["c5"]
+    T = [0.7, 3.5]
+    e = relib.Engine([N, N], T, rho, rc, skin, dt, 10, 5, engine=engine, watchdog_seconds=20)
+    L, xs, vs = injected(e, [N, N], T, rho, 0.05, 4000)
+    g = np.random.default_rng(3)
+    for r in range(2):
+        F, U = e.compute_forces(r)
+        idx = g.choice(N, size=40, replace=False)
+        Fo = np.array([oracle.force_on(xs[r], L[r], rc, int(i))[0] for i in idx])
+        rms = np.sqrt((Fo * Fo).sum(1).mean())
+        assert np.abs(F[idx] - Fo).max() / rms <= 1e-5, r
+        assert np.array_equal(e.query_forces(r)[idx], F[idx])
+    e.step(20)
+    out = [e.get_state(r) for r in range(2)]
+    e.close()
+    if engine == "persistent":
+        e2 = relib.Engine([N, N], T, rho, rc, skin, dt, 10, 5, engine="lockstep")
+        injected(e2, [N, N], T, rho, 0.05, 4000)
+        e2.step(20)
+        for r in range(2):
+            x2, v2 = e2.get_state(r)
+            assert np.array_equal(out[r][0], x2) and np.array_equal(out[r][1], v2), r
+        e2.close()
+
+
+@pytest.mark.parametrize("engine", ["lockstep", "persistent"])
+def test_list_overflow_is_reported(relib, engine):
+    """A configuration denser than the neighbour-list capacity allows (a
+    simple-cubic cluster of spacing 0.7, about 270 atoms within the list
+    radius of each against a capacity of 144) is reported as RE_EOVERFLOW;
+    the list writes are bounded, and the error stays set for the context."""
+    N = 512
+    e = relib.Engine([N], [1.0], 0.8442, 2.5, 0.3, 0.005, 10, 1, engine=engine, watchdog_seconds=10)
+    g = np.stack(np.meshgrid(*[np.arange(8)] * 3, indexing="ij"), -1).reshape(-1, 3)
+    L = e.query_box()[0]
+    x = W.snap_to_grid((g - 3.5) * 0.7, L)
+    with pytest.raises(relib.ReError) as err:
+        e.set_state(0, x, np.zeros((N, 3)))
+    assert err.value.code == relib.RE_EOVERFLOW
+    with pytest.raises(relib.ReError) as err:
+        e.step(1)
+    assert err.value.code == relib.RE_EOVERFLOW
+    e.close()

@@ -167,3 +167,46 @@ def test_explicit_images_brute_force(orc):
         F, U, _ = orc.forces(x, L, RC)
         assert U == pytest.approx(U_ref, rel=1e-12, abs=1e-12)
         assert np.allclose(F, F_ref, rtol=1e-11, atol=1e-11)
+
+
+def _force_on_all(orc, x, L, rc):
+    rows = [orc.force_on(x, L, rc, i) for i in range(len(x))]
+    return np.array([f for f, _ in rows]), np.array([e for _, e in rows])
+
+
+@pytest.mark.parametrize("rc", [2.5, 3.0])
+def test_force_on_rows(orc, rc):
+    """The one-atom force (the checker of sampled atoms in large systems)
+    equals the corresponding row of the all-pairs forces, and its pair-energy
+    sums add up to twice the potential energy (every pair seen from both of
+    its atoms)."""
+    L = 7.5
+    x = random_liquid(120, L, 21)
+    F, U, _ = orc.forces(x, L, rc)
+    Fr, e = _force_on_all(orc, x, L, rc)
+    scale = np.sqrt((F * F).sum(1).mean())
+    assert np.abs(Fr - F).max() <= 1e-13 * scale
+    assert e.sum() == pytest.approx(2.0 * U, rel=1e-13)
+    assert np.abs(Fr.sum(0)).max() < 1e-10  # Newton's third law, from the rows
+
+
+def test_force_on_is_minus_gradient(orc):
+    """The one-atom force is minus the derivative of the energy that the
+    one-atom energy sums define (U = half their total), by central
+    differences: a check that uses force_on alone."""
+    L = 6.0
+    x = random_liquid(50, L, 8)
+    h = 1e-6
+
+    def U_of(y):
+        return 0.5 * sum(orc.force_on(y, L, RC, i)[1] for i in range(len(y)))
+
+    rng = np.random.default_rng(4)
+    for _ in range(12):
+        i, k = int(rng.integers(50)), int(rng.integers(3))
+        Fi, _ = orc.force_on(x, L, RC, i)
+        xp, xm = x.copy(), x.copy()
+        xp[i, k] += h
+        xm[i, k] -= h
+        fd = -(U_of(xp) - U_of(xm)) / (2 * h)
+        assert fd == pytest.approx(Fi[k], rel=2e-6, abs=2e-6)
