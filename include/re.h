@@ -255,6 +255,18 @@ int re_set_schedule(re_ctx* ctx, const int64_t* join, int64_t A);
 int re_test_exchange(const double* U, const double* T, const int32_t* slot, int R,
                      uint64_t seed, int64_t attempt, int max_distance, uint8_t* decisions);
 
+/* re_test_exchange for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight driver loops, harnesses that forbid
+ * hipMalloc): the same arguments, rule and results, but the device staging
+ * of U, T, slot and the decisions is a fixed array inside the library (one
+ * per GPU, 84 KiB, held until the process ends) instead of allocations.  It
+ * runs on the current device and the null stream, and calls no allocating
+ * routine.  Limit: R <= 4096 (RE_EINVAL beyond, with the limit named).
+ * Calls that overlap on one GPU (from several host threads) share that
+ * array and race; serialise them.  Errors: RE_EINVAL, RE_EDEVICE. */
+int re_test_exchange_noalloc(const double* U, const double* T, const int32_t* slot, int R,
+                             uint64_t seed, int64_t attempt, int max_distance, uint8_t* decisions);
+
 /* Device random numbers, for testing (no context needed).
  * re_test_philox: n Philox4x32-10 blocks (Salmon et al., SC'11) of the
  * counters ctr[4i .. 4i+3] under key (key0, key1) into out[4i .. 4i+3].

@@ -108,6 +108,17 @@ static int fail(re_ctx* c, int code, const char* fmt, ...)
     return code;
 }
 
+int re::fail_noctx(int code, const char* fmt, ...)
+{
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_noctx_error = buf;
+    return code;
+}
+
 #define HIPCHK(ctx, expr)                                                                              \
     do {                                                                                               \
         hipError_t e_ = (expr);                                                                        \

@@ -164,4 +164,8 @@ hipError_t launch_test_philox(const uint32_t* ctr, uint32_t key0, uint32_t key1,
                               hipStream_t st);
 hipError_t launch_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int n, double* out, hipStream_t st);
 
+// Record the message of a failed context-free call (re_last_error(NULL))
+// and return code (re_host.cpp).
+int fail_noctx(int code, const char* fmt, ...);
+
 }  // namespace re

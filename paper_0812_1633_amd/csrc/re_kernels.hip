@@ -3,8 +3,11 @@
 // or for one replica (the plain per-replica form), plus the exchange kernel
 // and the test hooks.  The per-atom arithmetic lives in re_device.hpp.
 #include "re_device.hpp"
+#include "../../include/re.h"
 
 #include <algorithm>
+#include <cstring>
+#include <mutex>
 
 namespace re {
 
@@ -570,3 +573,68 @@ hipError_t launch_test_normals(int fp64, uint64_t seed, const uint32_t* ctr, int
 }
 
 }  // namespace re
+
+// ---------------------------------------------------------------------------
+// re_test_exchange without any allocation.  The staging of its inputs
+// (energies, ladder, slots) and of its decisions is a file-scope device
+// array, one copy per GPU; each device's copy is located once, with that
+// device current, and only that address is handed to copies and kernels.
+namespace {
+constexpr int kStaticMaxR = 4096;  // replicas per call
+constexpr size_t kStU = 0, kStT = 8 * (size_t)kStaticMaxR, kStSlot = 16 * (size_t)kStaticMaxR,
+                 kStDec = 20 * (size_t)kStaticMaxR, kStBytes = 21 * (size_t)kStaticMaxR;  // 84 KiB
+constexpr int kStaticMaxDevices = 64;
+std::mutex g_static_mu;
+unsigned char* g_static_ptr[kStaticMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStBytes];
+
+extern "C" int re_test_exchange_noalloc(const double* U, const double* T, const int32_t* slot, int R, uint64_t seed,
+                                        int64_t attempt, int max_distance, uint8_t* decisions)
+{
+    if (!U || !T || !slot || !decisions || R < 1 || max_distance < 1)
+        return re::fail_noctx(RE_EINVAL, "re_test_exchange_noalloc: bad arguments");
+    if (R > kStaticMaxR)
+        return re::fail_noctx(RE_EINVAL, "re_test_exchange_noalloc: R = %d exceeds its static staging of %d replicas",
+                              R, kStaticMaxR);
+    unsigned char seen[kStaticMaxR];
+    std::memset(seen, 0, (size_t)R);
+    for (int r = 0; r < R; ++r) {
+        if (slot[r] < 0 || slot[r] >= R || seen[slot[r]]++)
+            return re::fail_noctx(RE_EINVAL, "re_test_exchange_noalloc: slot is not a permutation");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return re::fail_noctx(RE_EDEVICE, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kStaticMaxDevices)
+        return re::fail_noctx(RE_EDEVICE, "re_test_exchange_noalloc: device index %d out of range", dev);
+    unsigned char* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_static_mu);
+        if (!g_static_ptr[dev]) {
+            void* p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !p)
+                return re::fail_noctx(RE_EDEVICE, "hipGetSymbolAddress of the static staging: %s",
+                                      hipGetErrorString(e));
+            g_static_ptr[dev] = static_cast<unsigned char*>(p);
+        }
+        base = g_static_ptr[dev];
+    }
+    double* dU = reinterpret_cast<double*>(base + kStU);
+    double* dT = reinterpret_cast<double*>(base + kStT);
+    int32_t* ds = reinterpret_cast<int32_t*>(base + kStSlot);
+    uint8_t* dd = base + kStDec;
+    // every word the kernel reads is written by this call's copies (U, T and
+    // slot for the R replicas) or by the kernel itself (decisions), so
+    // nothing left by an earlier call is read
+    e = hipMemcpy(dU, U, (size_t)R * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(dT, T, (size_t)R * 8, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(ds, slot, (size_t)R * 4, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = re::launch_test_exchange(dU, dT, ds, R, seed, attempt, max_distance, dd, nullptr);
+    if (e == hipSuccess && R > 1) e = hipMemcpy(decisions, dd, (size_t)(R - 1), hipMemcpyDeviceToHost);
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) return re::fail_noctx(RE_EDEVICE, "re_test_exchange_noalloc: %s", hipGetErrorString(e));
+    return RE_OK;
+}

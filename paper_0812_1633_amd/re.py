@@ -79,6 +79,7 @@ def lib():
         L.re_query_forces.argtypes = [vp, C.c_int, vp]
         L.re_set_schedule.argtypes = [vp, vp, i64]
         L.re_test_exchange.argtypes = [vp, vp, vp, C.c_int, u64, i64, C.c_int, vp]
+        L.re_test_exchange_noalloc.argtypes = [vp, vp, vp, C.c_int, u64, i64, C.c_int, vp]
         L.re_test_philox.argtypes = [vp, C.c_uint32, C.c_uint32, C.c_int, vp]
         L.re_test_normals.argtypes = [C.c_int, u64, vp, C.c_int, vp]
         L.re_profile.argtypes = [vp, C.c_int]
@@ -93,7 +94,7 @@ def lib():
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
                   "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count",
-                  "re_query_forces"):
+                  "re_query_forces", "re_test_exchange_noalloc"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -315,6 +316,19 @@ def re_test_exchange(U, T, slot, seed, attempt, max_distance=1):
     dec = np.zeros(max(1, R - 1), np.uint8)
     _check(lib().re_test_exchange(_ptr(U), _ptr(T), _ptr(slot), R, int(seed), int(attempt),
                                   int(max_distance), _ptr(dec)))
+    return dec[: R - 1]
+
+
+def re_test_exchange_noalloc(U, T, slot, seed, attempt, max_distance=1):
+    """re_test_exchange without any device allocation (the staging lives in
+    a fixed array inside the library; at most 4096 replicas)."""
+    U = np.ascontiguousarray(U, np.float64)
+    T = np.ascontiguousarray(T, np.float64)
+    slot = np.ascontiguousarray(slot, np.int32)
+    R = U.size
+    dec = np.zeros(max(1, R - 1), np.uint8)
+    _check(lib().re_test_exchange_noalloc(_ptr(U), _ptr(T), _ptr(slot), R, int(seed), int(attempt),
+                                          int(max_distance), _ptr(dec)))
     return dec[: R - 1]
 
 
