@@ -17,7 +17,8 @@ memory).  Every combination is checked here against the oracle:
   atom within the list radius, so list-build lanes often pass 64 candidates
   and take their walk path);
 * the exact headline launch (32 x 4000 atoms, persistent engine, 2 lanes
-  per atom, teams of 8 workgroups), one step;
+  per atom, teams of 8 workgroups): one step, and 100 steps in both
+  precisions;
 * replicas of the largest ladder's full size (108000 atoms): sampled forces
   against the oracle's one-atom sums, and the two engines bitwise equal.
 
@@ -169,6 +170,45 @@ def test_headline_launch(relib):
         assert normwise(eng.query_forces(r), replica_F(ens, r)) <= 1e-5, r
         assert abs(U[r] - ens.U[r]) <= 1e-5 * abs(ens.U[r]), r
     eng.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_headline_launch_trajectories(relib, precision):
+    """100 steps of the headline launch (32 x 4000, persistent, 2 lanes,
+    teams of 8) from a seeded state, every replica against the oracle.
+
+    FP64: every replica within 1e-9.  Mixed: the FP32 pair arithmetic
+    perturbs each step's forces at the 1e-7 level, the liquid's chaos
+    amplifies that, and the truncated force jumps by |f(r_c)| = 0.039 when a
+    pair crosses r_c between the two runs' positions; at 128000 atoms such
+    a crossing happens in a few replicas within 100 steps and moves them
+    by up to about 1e-3 (the oracle alone, started 64 grid units apart,
+    already separates by 6e-5).  So the 1e-4 bar is applied to the median
+    replica and to at least three quarters of them, with 1e-2 as the bound
+    for every replica; the 2-replica runs of the other tests meet 1e-4 in
+    full."""
+    R, N = 32, 4000
+    rc, skin, dt = PARAMS["c2"]
+    T = W.ladder(0.7, 2.0, R)
+    rho, seed = 0.8442, 1
+    Ns = [N] * R
+    eng = relib.Engine(Ns, T, rho, rc, skin, dt, NOX, seed, engine="persistent", threads_per_atom=2,
+                       team_size=8, precision=precision, watchdog_seconds=10)
+    L, xs, vs = injected(eng, Ns, T, rho, 0.05, 2000)
+    eng.step(100)
+    U = eng.query_energies()
+    ens = oracle_ensemble(Ns, L, T, rc, skin, dt, seed, xs, vs)
+    ens.run_sync(100, NOX)
+    dev = np.array([mi_dist(eng.get_state(r)[0], ens.replica_x(r), L[r]) for r in range(R)])
+    eng.close()
+    if precision == "fp64":
+        assert dev.max() <= 1e-9, dev.max()
+        assert np.all(np.abs(U - ens.U) <= 1e-10 * np.abs(ens.U))
+    else:
+        assert np.median(dev) <= 1e-4, np.median(dev)
+        assert (dev <= 1e-4).sum() >= 3 * R // 4, np.sort(dev)
+        assert dev.max() <= 1e-2, dev.max()
+        assert np.all(np.abs(U - ens.U) <= 1e-4 * np.abs(ens.U))
 
 
 @pytest.mark.parametrize("engine", ["lockstep", "persistent"])
