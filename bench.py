@@ -49,7 +49,7 @@ PEAK_FP32_UNPACKED_TFLOPS = 78.6
 # the hash of the kernel sources they were taken with: a changed kernel
 # reports traffic null until it is measured again.
 TRAFFIC = {
-    ("lj-32x4000", "persistent", 2): dict(fetch=351.7, write=93.6, src="8426a61382a89720"),
+    ("lj-32x4000", "persistent", 2): dict(fetch=70.66, write=66.07, src="6b3411ebd839e509"),
 }
 KERNEL_SOURCES = ("re_persist.hip", "re_persist.hpp", "re_device.hpp", "re_internal.hpp", "re_kernels.hip")
 
@@ -252,6 +252,9 @@ def main():
     atom_steps_launch = atoms if engine_used == "lockstep" else done / max(1, k_n)
     flops_launch = flop_per_atom * atom_steps_launch
     achieved = flops_launch / (k_ms * 1e-3) / 1e12 if k_ms > 0 else None
+    # the mixed form's list entries are 16-bit slots when every replica has at
+    # most 65536 atoms (policy PMixed16), 32-bit byte offsets otherwise
+    policy = "PMixed16" if int(N.max()) <= 65536 else "PMixed"
     tr = TRAFFIC.get((args.workload, engine_used, tpa_used))
     src = kernel_source_hash()
     traffic = None
@@ -263,7 +266,8 @@ def main():
                 "hbm_GBps_at_traffic": (traffic / (k_ms * 1e-3) / 1e9) if traffic and k_ms > 0 else None,
                 "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": (achieved / PEAK_FP32_UNPACKED_TFLOPS) if achieved else None,
-                "kernel": "k_force<PMixed,fused>" if engine_used == "lockstep" else "k_persist<PMixed,%d,false>" % tpa_used,
+                "kernel": ("k_force<%s,fused>" % policy) if engine_used == "lockstep"
+                else "k_persist<%s,%d,false>" % (policy, tpa_used),
                 "kernel_ms": k_ms, "launches_timed": k_n, "atom_steps_per_launch": atom_steps_launch,
                 "flop_per_atom_step": float(flop_per_atom), "kernel_src": src,
                 "wall_over_kernel": ((t1 - t0) * 1e3 / (k_ms * k_n)) if (engine_used != "lockstep" and k_ms > 0)

@@ -101,6 +101,10 @@ struct PMixed {
     using vel_t = float4;
     using real = float;
     static constexpr bool kF64 = false;
+    // neighbour-list entries: the neighbour's byte offset from the replica's
+    // first position (32 bits)
+    using entry_t = uint32_t;
+    static constexpr bool kSlotEntries = false;
     __device__ static pos_t* pos(const DevState& d, int b) { return d.posi[b]; }
     __device__ static vel_t* vel(const DevState& d) { return d.velf; }
     __device__ static vel_t* velt(const DevState& d) { return d.veltf; }
@@ -162,6 +166,8 @@ struct PF64 {
     using vel_t = double4;
     using real = double;
     static constexpr bool kF64 = true;
+    using entry_t = uint32_t;  // byte offsets, as in PMixed
+    static constexpr bool kSlotEntries = false;
     __device__ static pos_t* pos(const DevState& d, int b) { return d.posd[b]; }
     __device__ static vel_t* vel(const DevState& d) { return d.veld; }
     __device__ static vel_t* velt(const DevState& d) { return d.veltd; }
@@ -202,6 +208,36 @@ struct PF64 {
         return dx * dx + dy * dy + dz * dz < rd.rl2d;
     }
 };
+
+// The mixed form with 16-bit neighbour-list entries holding the neighbour's
+// slot (its byte offset is the slot times 16): for contexts whose replicas
+// all have at most 65536 atoms.  Half the list bytes of PMixed.
+struct PMixed16 : PMixed {
+    using entry_t = uint16_t;
+    static constexpr bool kSlotEntries = true;
+};
+
+// The byte offset of a list entry's neighbour from the replica's first
+// position.
+template <class P>
+__device__ __forceinline__ uint32_t entry_offset(uint32_t v)
+{
+    if constexpr (P::kSlotEntries)
+        return v * (uint32_t)sizeof(typename P::pos_t);
+    else
+        return v;
+}
+
+// Entries are padded, per atom, with entries naming the atom itself up to a
+// whole number of groups of 4 rows of tpa entries (at most the capacity M, a
+// multiple of 32), so that the force loop reads whole groups without
+// per-entry bounds; the self pair has r = 0 and is excluded by the force.
+__host__ __device__ constexpr int padded_entries(int n, int tpa, int M)
+{
+    const int g = 4 * tpa;
+    const int p = (n + g - 1) / g * g;
+    return p < M ? p : M;
+}
 
 template <class P>
 __device__ __forceinline__ void set_xyz(typename P::vel_t& v, typename P::real x, typename P::real y, typename P::real z)
@@ -654,15 +690,23 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         incl += q >= 4 ? s4 : 0;
     }
     int o = incl - cnt;
-    // entry o of atom i: word ((o / tpa) Np + i) tpa + o % tpa of the list
-    // (tpa a power of two)
-    uint32_t* nl = d.nl + rd.nl_base;
+    // entry o of atom i: element ((o / tpa) Np + i) tpa + o % tpa of the
+    // list (tpa a power of two)
+    using E = typename P::entry_t;
+    E* nl = reinterpret_cast<E*>(d.nl) + rd.nl_base;
     const int ltpa = __builtin_ctz((unsigned)tpa);
     const uint32_t jump = (uint32_t)rd.Np * (uint32_t)tpa - (uint32_t)(tpa - 1);
     uint32_t e = ((uint32_t)o >> ltpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
                  (uint32_t)(o & (tpa - 1));
+    // the entry of slot j: the slot itself, or its byte offset
+    auto value = [&](int j) -> E {
+        if constexpr (P::kSlotEntries)
+            return (E)j;
+        else
+            return (E)((uint32_t)j * (uint32_t)sizeof(typename P::pos_t));
+    };
     auto put = [&](int j) {
-        if ((unsigned)o < (unsigned)M) nl[e] = (uint32_t)j * (uint32_t)sizeof(typename P::pos_t);
+        if ((unsigned)o < (unsigned)M) nl[e] = value(j);
         ++o;
         e += (o & (tpa - 1)) ? 1u : jump;
     };
@@ -681,10 +725,16 @@ __device__ __forceinline__ void list_rows(const DevState& d, const RepDev& rd, c
         put(32 + k + lds[2 * (rhi + __popc(bhi & ((2u << k) - 1u))) + 1]);
     }
     if (T > 64) walk(put);
-    // the group's last lane holds the total
+    // the group's last lane holds the total; it pads the atom's entries
+    // with self entries to whole groups of rows
     if (act && q == LPA - 1) {
-        d.nn[rd.base + i] = incl < M ? incl : M;
+        const int n = incl < M ? incl : M;
+        d.nn[rd.base + i] = n;
         if (incl > M) atomicOr(d.overflow, 1u);
+        const int np = padded_entries(n, tpa, M);
+        for (int k = n; k < np; ++k)
+            nl[((uint32_t)k >> ltpa) * (uint32_t)rd.Np * (uint32_t)tpa + (uint32_t)i * (uint32_t)tpa +
+               (uint32_t)(k & (tpa - 1))] = value(i);
     }
 }
 
@@ -714,20 +764,22 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
         pi = pos[ia];
         const int nnb = d.nn[rd.base + ia];
         // list row kk of this lane: the replica's row base (the same for the
-        // whole wave) plus the lane's 32-bit byte offset
-        const char* __restrict__ nlb = reinterpret_cast<const char*>(d.nl + rd.nl_base);
-        const uint32_t eo = (uint32_t)(ia * TPA + q) * (uint32_t)sizeof(uint32_t);
-        const size_t rowb = (size_t)rd.Np * TPA * sizeof(uint32_t);
-        auto entry = [&](int kk) { return *reinterpret_cast<const uint32_t*>(nlb + (size_t)kk * rowb + eo); };
-        const int nrow = (nnb - q + TPA - 1) / TPA;
+        // whole wave) plus the lane's 32-bit byte offset; rows past the
+        // atom's entries up to a whole group of 4 hold the atom itself
+        using E = typename P::entry_t;
+        const char* __restrict__ nlb = reinterpret_cast<const char*>(reinterpret_cast<const E*>(d.nl) + rd.nl_base);
+        const uint32_t eo = (uint32_t)(ia * TPA + q) * (uint32_t)sizeof(E);
+        const size_t rowb = (size_t)rd.Np * TPA * sizeof(E);
+        const int nrow = padded_entries(nnb, TPA, sa.M) / TPA;
         if constexpr (P::kF64) {
+            auto entry = [&](int kk) { return (uint32_t)*reinterpret_cast<const E*>(nlb + (size_t)kk * rowb + eo); };
             const double rc2 = rd.rc2d;
             for (int kk = 0; kk < nrow; ++kk) {
                 const typename P::pos_t pj = *reinterpret_cast<const typename P::pos_t*>(pb + entry(kk));
                 double dx, dy, dz;
                 P::diff(pi, pj, rd, dx, dy, dz);
                 const double r2 = dx * dx + dy * dy + dz * dz;
-                if (r2 < rc2) {
+                if (r2 < rc2 && r2 > 0.0) {  // (r = 0: the atom itself)
                     const double ir2 = 1.0 / r2;
                     const double ir6 = ir2 * ir2 * ir2;
                     const double ff = 24.0 * ir2 * ir6 * (2.0 * ir6 - 1.0);
@@ -741,8 +793,8 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
             const float rc2 = rd.rc2f, lo = rd.near_lo, hi = rd.near_hi, is2 = rd.inv_s2f;
             const float ushift = (float)sa.ushiftd;
             const uint64_t thr = rd.rc2_exact;
-            // one pair: pj is the neighbour, ok false for padding entries
-            auto pair = [&](const int4& pj, bool ok) {
+            // one pair; the atom itself (r = 0, a padding entry) is excluded
+            auto pair = [&](const int4& pj) {
                 const int ix = PMixed::wrapdiff(pi.x, pj.x);
                 const int iy = PMixed::wrapdiff(pi.y, pj.y);
                 const int iz = PMixed::wrapdiff(pi.z, pj.z);
@@ -755,7 +807,7 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
                                         (uint64_t)((int64_t)iz * iz);
                     in = e2 < thr;
                 }
-                in = in && ok;
+                in = in && r2 > 0.0f;
                 const float ir2 = __builtin_amdgcn_rcpf(r2) * is2;
                 const float ir6 = ir2 * ir2 * ir2;
                 const float ff = in ? ir2 * ir6 * __builtin_fmaf(48.0f, ir6, -24.0f) : 0.0f;
@@ -764,49 +816,37 @@ __device__ __forceinline__ void force_sum(const DevState& d, const StepArgs& sa,
                 fz = __builtin_fmaf(ff, dz, fz);
                 if constexpr (kEnergy) e += in ? __builtin_fmaf(4.0f * ir6, ir6, -4.0f * ir6) - ushift : 0.0f;
             };
-            // four neighbours in flight: the indices of the next four are
-            // loaded while the current four are computed
+            // four neighbours in flight: the entries of the next four rows are
+            // loaded while the current four pairs are computed (the loads of
+            // the group after the last are past the atom's rows; their values
+            // are not used)
             constexpr int U = 4;
-            // (rows past the atom's own entries are read unconditionally -- the
-            // list allocation has kListSlackRows rows of slack -- and replaced
-            // by the atom itself, which the ok flag then masks)
-            // (the row test of a prefetch is the valid flag of the next four)
-            const uint32_t self = (uint32_t)ia * (uint32_t)sizeof(int4);
             // the list words through a buffer resource over the replica's
             // block: the row offset goes in a scalar register and the lane's
-            // in a 32-bit vector register, so an index load needs no vector
-            // address arithmetic (the host keeps a block under 2^32 bytes)
+            // in a 32-bit vector register, so an entry load needs no vector
+            // address arithmetic (the host keeps a block under 2^32 bytes;
+            // loads past the block return 0)
             const __amdgpu_buffer_rsrc_t nlr = __builtin_amdgcn_make_buffer_rsrc(
-                (void*)nlb, (short)0, (int)((uint32_t)rd.Np * (uint32_t)sa.M * (uint32_t)sizeof(uint32_t)),
+                (void*)nlb, (short)0, (int)((uint32_t)rd.Np * (uint32_t)sa.M * (uint32_t)sizeof(E)),
                 0x00020000);  // (descriptor word 3 of gfx9: 32-bit elements)
             const uint32_t rowb32 = (uint32_t)rowb;
-            auto bentry = [&](int kk) {
-                return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(nlr, (int)eo, (int)((uint32_t)kk * rowb32), 0);
+            auto bentry = [&](int kk) -> uint32_t {
+                if constexpr (sizeof(E) == 2)
+                    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(nlr, (int)eo, (int)((uint32_t)kk * rowb32), 0);
+                else
+                    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(nlr, (int)eo, (int)((uint32_t)kk * rowb32), 0);
             };
             uint32_t jn[U];
-            bool okn[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const uint32_t ld = bentry(u);
-                okn[u] = u < nrow;
-                jn[u] = okn[u] ? ld : self;
-            }
+            for (int u = 0; u < U; ++u) jn[u] = entry_offset<P>(bentry(u));
             for (int kk = 0; kk < nrow; kk += U) {
                 int4 pj[U];
-                bool ok[U];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    pj[u] = *reinterpret_cast<const int4*>(pb + jn[u]);
-                    ok[u] = okn[u];
-                }
+                for (int u = 0; u < U; ++u) pj[u] = *reinterpret_cast<const int4*>(pb + jn[u]);
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const uint32_t ld = bentry(kk + U + u);
-                    okn[u] = kk + U + u < nrow;
-                    jn[u] = okn[u] ? ld : self;
-                }
+                for (int u = 0; u < U; ++u) jn[u] = entry_offset<P>(bentry(kk + U + u));
 #pragma unroll
-                for (int u = 0; u < U; ++u) pair(pj[u], ok[u]);
+                for (int u = 0; u < U; ++u) pair(pj[u]);
             }
         }
     }

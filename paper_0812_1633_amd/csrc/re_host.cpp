@@ -270,6 +270,7 @@ static StepArgs base_args(re_ctx* c)
     a.block = c->cfg.block;
     a.tpa = c->cfg.tpa;
     a.M = c->cfg.M;
+    a.n16 = c->cfg.n16;
     a.h = 0.5 * c->dt;
     a.c1 = c->c1;
     a.ushiftd = c->ushift;
@@ -492,7 +493,7 @@ static int plan_persistent(re_ctx* c, int team_opt)
     int dev = 0, cus = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
     HIPCHK(c, hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HIPCHK(c, persist_occupancy(c->prec == RE_FP64, c->cfg.tpa, c->thermo == kThermoSVR, &occ));
+    HIPCHK(c, persist_occupancy(c->prec == RE_FP64, c->cfg.n16 != 0, c->cfg.tpa, c->thermo == kThermoSVR, &occ));
     const int cap = cus * std::max(0, occ);
     const int R = c->R;
     c->pers_ok = false;
@@ -776,10 +777,16 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     for (double q : c->rho) rho_max = std::max(rho_max, q);
     {
         // expected neighbours within the list radius, with room for density
-        // fluctuations; a multiple of 8 (so of every threads_per_atom)
+        // fluctuations; a multiple of 32 (whole groups of 4 rows at every
+        // threads_per_atom)
         const double expect = 4.18879020478639 * rlist * rlist * rlist * rho_max;
-        c->cfg.M = ((int)std::ceil(1.4 * expect) + 32 + 7) / 8 * 8;
+        c->cfg.M = ((int)std::ceil(1.4 * expect) + 32 + 31) / 32 * 32;
     }
+
+    // 16-bit list entries (the neighbour's slot) when every replica of the
+    // mixed form has at most 65536 atoms; 32-bit byte offsets otherwise
+    c->cfg.n16 = c->prec == RE_MIXED && *std::max_element(N_atoms, N_atoms + R) <= 65536 ? 1 : 0;
+    const int64_t esz = c->cfg.n16 ? 2 : 4;
 
     // per-replica layout
     c->rep.resize(R);
@@ -808,9 +815,9 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         c->cells_max = std::max(c->cells_max, nc * nc * nc);
         rd.nl_base = nl;
         nl += (int64_t)rd.Np * c->cfg.M;
-        // list words of one replica are addressed with 32-bit byte offsets
+        // list entries of one replica are addressed with 32-bit byte offsets
         // (with the slack rows read past the block)
-        const int64_t nl_bytes = ((int64_t)rd.Np * c->cfg.M + (int64_t)kListSlackRows * 8 * rd.Np) * 4;
+        const int64_t nl_bytes = ((int64_t)rd.Np * c->cfg.M + (int64_t)kListSlackRows * 8 * rd.Np) * esz;
         if (nl_bytes >= ((int64_t)1 << 32)) {
             delete c;
             return fail(nullptr, RE_EINVAL, "replica %d: its neighbour-list block (%lld bytes) reaches 2^32 bytes", r,
@@ -895,7 +902,11 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.cellid, slots);
     ALLOC(d.rank, slots);
     ALLOC(d.cell_start, cells);
-    ALLOC(d.nl, nl + (int64_t)kListSlackRows * 8 * ((c->nmax + 63) / 64 * 64));
+    {
+        unsigned char* nlp = nullptr;
+        ALLOC(nlp, (nl + (int64_t)kListSlackRows * 8 * ((c->nmax + 63) / 64 * 64)) * esz);
+        d.nl = nlp;
+    }
     ALLOC(d.nn, slots);
     ALLOC(d.rep, R);
     ALLOC(d.slot, R);

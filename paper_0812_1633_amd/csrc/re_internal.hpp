@@ -83,7 +83,7 @@ struct DevState {
     int32_t* cellid;    // reorder scratch
     int32_t* rank;      // reorder scratch
     int32_t* cell_start;// per replica ncell^3 + 1
-    uint32_t* nl;       // neighbour lists
+    void* nl;           // neighbour lists (entries of the precision policy's entry_t)
     int32_t* nn;        // neighbours per atom
     // per replica
     RepDev* rep;
@@ -114,7 +114,8 @@ struct BlockTable {
 struct LaunchCfg {
     int block;      // threads per block of the wide kernels
     int tpa;        // force-kernel lanes per atom
-    int M;          // neighbour-list capacity per atom
+    int M;          // neighbour-list capacity per atom (a multiple of 32)
+    int n16;        // mixed form: 16-bit list entries
     int64_t log_cap;
 };
 
@@ -127,7 +128,8 @@ struct StepArgs {
     int blk_off;      // first block-table entry (wide kernels)
     int block;        // threads per block (wide kernels)
     int tpa;          // force-kernel lanes per atom
-    int M;            // neighbour-list capacity per atom
+    int M;            // neighbour-list capacity per atom (a multiple of 32)
+    int n16;          // mixed form: 16-bit list entries (every replica <= 65536 atoms)
     int force_all;    // reorder/list: ignore the flags
     int apply_alpha;  // start: multiply v by the last exchange factor
     BlockTable tab;   // block table of the wide kernels

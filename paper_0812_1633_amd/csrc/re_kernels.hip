@@ -464,7 +464,9 @@ hipError_t launch_start(bool fp64, const DevState& d, const StepArgs& sa, int nb
     return fp64 ? start_t<PF64>(d, sa, nblk, st) : start_t<PMixed>(d, sa, nblk, st);
 }
 
-template <class P>
+// P: the precision policy of the reorder; PL: that of the list build (its
+// entry type)
+template <class P, class PL>
 static hipError_t rebuild_t(const DevState& d, const StepArgs& sa, int nrep, int64_t atoms, bool wide, hipStream_t st)
 {
     hipLaunchKernelGGL(k_rebuild_table, dim3(1), dim3(1024), 0, st, d, sa, nrep);
@@ -483,7 +485,7 @@ static hipError_t rebuild_t(const DevState& d, const StepArgs& sa, int nrep, int
         hipLaunchKernelGGL(k_reorder<P>, dim3(std::min(nrep, 1024)), dim3(kReorderThreads), 0, st, d, sa, nrep);
     }
     const int gblk = (int)std::min<int64_t>(atoms / kListAPB + nrep, 8192);
-    hipLaunchKernelGGL(k_listrows<P>, dim3(gblk), dim3(256), 0, st, d, sa, nrep);
+    hipLaunchKernelGGL(k_listrows<PL>, dim3(gblk), dim3(256), 0, st, d, sa, nrep);
     return hipGetLastError();
 }
 
@@ -491,7 +493,9 @@ hipError_t launch_rebuild(bool fp64, const DevState& d, const StepArgs& sa, int 
                           hipStream_t st)
 {
     if (nrep <= 0) return hipSuccess;
-    return fp64 ? rebuild_t<PF64>(d, sa, nrep, atoms, wide, st) : rebuild_t<PMixed>(d, sa, nrep, atoms, wide, st);
+    if (fp64) return rebuild_t<PF64, PF64>(d, sa, nrep, atoms, wide, st);
+    return sa.n16 ? rebuild_t<PMixed, PMixed16>(d, sa, nrep, atoms, wide, st)
+                  : rebuild_t<PMixed, PMixed>(d, sa, nrep, atoms, wide, st);
 }
 
 template <class P, int MODE>
@@ -523,7 +527,8 @@ static hipError_t force_t(StepMode mode, const DevState& d, const StepArgs& sa, 
 hipError_t launch_force(bool fp64, StepMode mode, const DevState& d, const StepArgs& sa, int nblk, hipStream_t st)
 {
     if (nblk <= 0) return hipSuccess;
-    return fp64 ? force_t<PF64>(mode, d, sa, nblk, st) : force_t<PMixed>(mode, d, sa, nblk, st);
+    if (fp64) return force_t<PF64>(mode, d, sa, nblk, st);
+    return sa.n16 ? force_t<PMixed16>(mode, d, sa, nblk, st) : force_t<PMixed>(mode, d, sa, nblk, st);
 }
 
 hipError_t launch_energy(bool fp64, const DevState& d, const StepArgs& sa, int nrep, hipStream_t st)

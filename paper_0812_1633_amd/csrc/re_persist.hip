@@ -755,6 +755,7 @@ hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, i
     if (e != hipSuccess) return e;
     const bool svr = pa.sa.thermo == kThermoSVR;
     if (fp64) return svr ? persist_t<PF64, true>(d, pa, nblk, st) : persist_t<PF64, false>(d, pa, nblk, st);
+    if (pa.sa.n16) return svr ? persist_t<PMixed16, true>(d, pa, nblk, st) : persist_t<PMixed16, false>(d, pa, nblk, st);
     return svr ? persist_t<PMixed, true>(d, pa, nblk, st) : persist_t<PMixed, false>(d, pa, nblk, st);
 }
 
@@ -781,10 +782,11 @@ static const void* persist_kernel(int tpa)
     }
 }
 
-hipError_t persist_occupancy(bool fp64, int tpa, bool svr, int* blocks_per_cu)
+hipError_t persist_occupancy(bool fp64, bool n16, int tpa, bool svr, int* blocks_per_cu)
 {
-    const void* f = fp64 ? (svr ? persist_kernel<PF64, true>(tpa) : persist_kernel<PF64, false>(tpa))
-                         : (svr ? persist_kernel<PMixed, true>(tpa) : persist_kernel<PMixed, false>(tpa));
+    const void* f = fp64  ? (svr ? persist_kernel<PF64, true>(tpa) : persist_kernel<PF64, false>(tpa))
+                    : n16 ? (svr ? persist_kernel<PMixed16, true>(tpa) : persist_kernel<PMixed16, false>(tpa))
+                          : (svr ? persist_kernel<PMixed, true>(tpa) : persist_kernel<PMixed, false>(tpa));
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, f, 1024, 0);
 }
 

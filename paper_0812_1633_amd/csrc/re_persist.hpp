@@ -63,6 +63,6 @@ struct PersistArgs {
 };
 
 hipError_t launch_persist(bool fp64, const DevState& d, const PersistArgs& pa, int nblk, int nteams, hipStream_t st);
-hipError_t persist_occupancy(bool fp64, int tpa, bool svr, int* blocks_per_cu);
+hipError_t persist_occupancy(bool fp64, bool n16, int tpa, bool svr, int* blocks_per_cu);
 
 }  // namespace re
