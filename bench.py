@@ -128,6 +128,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1000)
     ap.add_argument("--workload", default="lj-32x4000")
     ap.add_argument("--engine", default=None, help="persistent | lockstep (default: autotuned)")
+    ap.add_argument("--tpa", type=int, default=0, help="force lanes per atom with --engine (default: 4)")
     ap.add_argument("--melt-steps", type=int, default=500,
                     help="input preparation: steps at T = 1.5 from the FCC start (0: start from FCC)")
     ap.add_argument("--equil-steps", type=int, default=500,
@@ -169,6 +170,7 @@ def main():
     tune = {}
     if args.engine:
         tune["engine"] = args.engine
+        tune["threads_per_atom"] = args.tpa
     else:
         tune["autotune"] = True
         import tempfile
@@ -180,6 +182,11 @@ def main():
     progress("%s: %d replicas, %d atoms; creating the context" % (args.workload, Rn, atoms))
     eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune)
     engine_used, tpa_used, team_used = eng.query_config()
+    lanes = eng.query_lanes()
+    lanes_used = (int(lanes[0]) if len(set(lanes.tolist())) == 1
+                  else {"%d..%d atoms" % (2 ** k, 2 ** (k + 1) - 1): sorted(set(int(t) for t, n in zip(lanes, N)
+                                                                               if int(np.log2(n)) == k))[0]
+                        for k in sorted(set(int(np.log2(n)) for n in N))})
     start = "FCC lattice, Maxwell-Boltzmann velocities at the ladder"
     if args.melt_steps > 0:
         progress("input preparation: %d steps at T = 1.5, then %d at the ladder" % (args.melt_steps,
@@ -266,7 +273,7 @@ def main():
                 "hbm_GBps_at_traffic": (traffic / (k_ms * 1e-3) / 1e9) if traffic and k_ms > 0 else None,
                 "peak_unpacked_fp32": PEAK_FP32_UNPACKED_TFLOPS,
                 "frac_unpacked": (achieved / PEAK_FP32_UNPACKED_TFLOPS) if achieved else None,
-                "kernel": ("k_force<%s,fused>" % policy) if engine_used == "lockstep"
+                "kernel": ("k_force<%s,fused,%d>" % (policy, tpa_used)) if engine_used == "lockstep"
                 else "k_persist<%s,%d,false>" % (policy, tpa_used),
                 "kernel_ms": k_ms, "launches_timed": k_n, "atom_steps_per_launch": atom_steps_launch,
                 "flop_per_atom_step": float(flop_per_atom), "kernel_src": src,
@@ -334,7 +341,7 @@ def main():
     svr = None
     if args.svr_steps > 0:
         svr = other_form("mixed, velocity rescale", args.svr_steps, precision="mixed", form="batched",
-                         thermostat="svr", engine=engine_used, threads_per_atom=tpa_used)
+                         thermostat="svr", engine=engine_used, threads_per_atom_per_replica=lanes)
 
     # ---- CPU leg: the oracle timed on a bounded sample of the workload ----
     cpu = None
@@ -364,6 +371,7 @@ def main():
                       "start": start, "exchange": "synchronous",
                       "precision": "FP32 pair arithmetic, 32-bit fixed-point positions, FP64 energies/exchange",
                       "engine": engine_used, "threads_per_atom": tpa_used, "team_size": team_used,
+                      "lanes_per_replica": lanes_used,
                       "tuning": "explicit" if args.engine else "autotuned",
                       "parallelism": "replicas batched on 1 GPU"},
            "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, "batched_fp64": fp64,

@@ -100,11 +100,16 @@ typedef struct {
     int block_size;              /* threads per block of the wide kernels; 0: auto */
     int team_size;               /* persistent engine: workgroups per replica; 0: auto */
     const char* tune_cache;      /* autotuner JSON cache path; NULL: no cache file */
-    int autotune;                /* nonzero: choose the batched engine and
-                                    threads_per_atom by timing short runs of each
-                                    candidate on throwaway contexts of the same
-                                    workload (or take the choice from tune_cache);
-                                    explicit engine/threads_per_atom settings are
+    int autotune;                /* nonzero: choose the batched engine, the
+                                    lockstep block size and the force lanes per
+                                    atom by timing short runs of each candidate
+                                    on throwaway contexts of the same workload
+                                    (or take the choice from tune_cache): first
+                                    one lane count for all replicas, then, for
+                                    ladders whose replicas fall into several
+                                    size classes (floor(log2 N)), a lane count
+                                    per class where that is at least 2 % faster;
+                                    explicit engine / block / lane settings are
                                     then ignored */
     int team_barrier;            /* persistent engine's barrier between the
                                     workgroups of one replica: RE_BARRIER_AUTO
@@ -126,6 +131,16 @@ typedef struct {
                                     this many microseconds, so that tests can
                                     check that results do not depend on the
                                     timing of the members; 0 = off         */
+    const int32_t* threads_per_atom_per_replica;
+                                 /* R values (1, 2, 4 or 8): force lanes per atom
+                                    of each replica (its force pass and list
+                                    layout), overriding threads_per_atom; the
+                                    kernels then choose per replica (per block
+                                    in the lockstep engine, per team in the
+                                    persistent one).  NULL: threads_per_atom
+                                    for every replica.  With autotune, the
+                                    tuner may set it per size class
+                                    (floor(log2 N)); see re_query_lanes   */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */
@@ -288,9 +303,13 @@ int re_query_kernel_time(re_ctx* ctx, double* mean_ms, int64_t* n);
 
 /* The launch configuration the context runs with (after autotuning):
  * engine (RE_LOCKSTEP | RE_PERSISTENT; RE_PLAIN form: RE_LOCKSTEP),
- * threads_per_atom, and the persistent team size of replica 0 (0 when the
+ * threads_per_atom (0 when it differs between replicas; see
+ * re_query_lanes), and the persistent team size of replica 0 (0 when the
  * persistent engine is not available). */
 int re_query_config(re_ctx* ctx, int* engine, int* threads_per_atom, int* team_size);
+
+/* Force lanes per atom of each replica (R values). */
+int re_query_lanes(re_ctx* ctx, int32_t* tpa);
 
 /* Free everything owned by the context (NULL is allowed). */
 void re_destroy(re_ctx* ctx);

@@ -39,6 +39,7 @@ struct re_ctx {
     double ushift = 0, c1 = 0;
     double watchdog = 10.0;
     std::vector<int32_t> N;
+    std::vector<int> tpa_r;  // force lanes per atom of each replica
     std::vector<double> rho, L, Tl;
     std::vector<RepDev> rep;
     // device
@@ -312,8 +313,8 @@ static int check_overflow(re_ctx* c)
 
 // ---------------------------------------------------------------------------
 // block tables
-static void table_contiguous(const re_ctx* c, int apb, std::vector<int32_t>& brep, std::vector<int32_t>& ba0,
-                             std::vector<int32_t>& start, std::vector<int32_t>& count)
+static void table_contiguous(const re_ctx* c, const std::vector<int>& apb, std::vector<int32_t>& brep,
+                             std::vector<int32_t>& ba0, std::vector<int32_t>& start, std::vector<int32_t>& count)
 {
     brep.clear();
     ba0.clear();
@@ -321,7 +322,7 @@ static void table_contiguous(const re_ctx* c, int apb, std::vector<int32_t>& bre
     count.assign(c->R, 0);
     for (int r = 0; r < c->R; ++r) {
         start[r] = (int)brep.size();
-        for (int a0 = 0; a0 < c->N[r]; a0 += apb) {
+        for (int a0 = 0; a0 < c->N[r]; a0 += apb[r]) {
             brep.push_back(r);
             ba0.push_back(a0);
         }
@@ -333,7 +334,8 @@ static void table_contiguous(const re_ctx* c, int apb, std::vector<int32_t>& bre
 // 8 XCDs, so the blocks of one replica sit at ids of one residue mod 8 and
 // share that XCD's L2; replicas are spread over the XCDs by atom count,
 // largest first.
-static void table_interleaved(const re_ctx* c, int apb, std::vector<int32_t>& brep, std::vector<int32_t>& ba0)
+static void table_interleaved(const re_ctx* c, const std::vector<int>& apb, std::vector<int32_t>& brep,
+                              std::vector<int32_t>& ba0)
 {
     const int X = 8;
     std::vector<std::vector<std::pair<int, int>>> bins(X);
@@ -343,7 +345,7 @@ static void table_interleaved(const re_ctx* c, int apb, std::vector<int32_t>& br
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return c->N[a] > c->N[b]; });
     for (int r : order) {
         const int x = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        for (int a0 = 0; a0 < c->N[r]; a0 += apb) bins[x].push_back({r, a0});
+        for (int a0 = 0; a0 < c->N[r]; a0 += apb[r]) bins[x].push_back({r, a0});
         load[x] += c->N[r];
     }
     size_t depth = 0;
@@ -371,7 +373,9 @@ static int build_tables(re_ctx* c)
 {
     std::vector<int32_t> brep, ba0;
     int rc;
-    const int apb1 = c->cfg.block, apbF = c->cfg.block / c->cfg.tpa;
+    // (the force kernels' blocks hold blockDim / tpa atoms of their replica)
+    std::vector<int> apb1(c->R, c->cfg.block), apbF(c->R);
+    for (int r = 0; r < c->R; ++r) apbF[r] = c->cfg.block / c->tpa_r[r];
     table_contiguous(c, apb1, brep, ba0, c->c1_start, c->c1_count);
     if ((rc = upload_table(c, brep, ba0, c->ct1))) return rc;
     table_contiguous(c, apbF, brep, ba0, c->cF_start, c->cF_count);
@@ -708,6 +712,12 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.threads_per_atom && o.threads_per_atom != 1 && o.threads_per_atom != 2 && o.threads_per_atom != 4 &&
         o.threads_per_atom != 8)
         return fail(nullptr, RE_EINVAL, "threads_per_atom must be 1, 2, 4 or 8");
+    if (o.threads_per_atom_per_replica)
+        for (int r = 0; r < R; ++r) {
+            const int t = o.threads_per_atom_per_replica[r];
+            if (t != 1 && t != 2 && t != 4 && t != 8)
+                return fail(nullptr, RE_EINVAL, "threads_per_atom_per_replica[%d] must be 1, 2, 4 or 8", r);
+        }
     if (o.block_size && o.block_size != 64 && o.block_size != 128 && o.block_size != 256)
         return fail(nullptr, RE_EINVAL, "block_size must be 64, 128 or 256");
     const double gamma = o.gamma_set ? o.gamma : 1.0;
@@ -715,6 +725,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     if (o.thermostat != RE_LANGEVIN && o.thermostat != RE_SVR) return fail(nullptr, RE_EINVAL, "bad thermostat");
     if (!(o.svr_tau >= 0)) return fail(nullptr, RE_EINVAL, "svr_tau must be >= 0");
     const double tau = o.svr_tau > 0 ? o.svr_tau : 0.5;
+    std::vector<int32_t> tuned_tpa;  // per replica, from the autotuner's size classes
     if (o.autotune && o.form == RE_BATCHED) {
         // the engine and lanes per atom of this size class: cached, or timed
         const std::string key =
@@ -727,7 +738,16 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         }
         o.batched_engine = ch.engine;
         o.threads_per_atom = ch.tpa;
+        if (ch.block) o.block_size = ch.block;
         o.autotune = 0;
+        tuned_tpa.assign(R, ch.tpa);
+        bool per_class = false;
+        for (int r = 0; r < R; ++r) {
+            const int k = tune_class(N_atoms[r]);
+            if (ch.cls_tpa[k]) tuned_tpa[r] = ch.cls_tpa[k];
+            per_class |= tuned_tpa[r] != ch.tpa;
+        }
+        o.threads_per_atom_per_replica = per_class ? tuned_tpa.data() : nullptr;
     }
     if (o.form == RE_PLAIN && o.exchange_mode == RE_ASYNC)
         return fail(nullptr, RE_EINVAL, "the plain per-replica form runs synchronous exchanges only");
@@ -772,6 +792,14 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     // launch configuration
     c->cfg.block = o.block_size ? o.block_size : 256;
     c->cfg.tpa = o.threads_per_atom ? o.threads_per_atom : 4;
+    c->tpa_r.assign(R, c->cfg.tpa);
+    if (o.threads_per_atom_per_replica) {
+        // lanes per atom per replica; the kernels dispatch per replica
+        // (cfg.tpa = 0) unless every replica has the same
+        for (int r = 0; r < R; ++r) c->tpa_r[r] = o.threads_per_atom_per_replica[r];
+        const bool uniform = std::all_of(c->tpa_r.begin(), c->tpa_r.end(), [&](int t) { return t == c->tpa_r[0]; });
+        c->cfg.tpa = uniform ? c->tpa_r[0] : 0;
+    }
     c->cfg.log_cap = o.log_capacity > 0 ? o.log_capacity : (int64_t)1 << 18;
     double rho_max = 0;
     for (double q : c->rho) rho_max = std::max(rho_max, q);
@@ -797,6 +825,7 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         std::memset(&rd, 0, sizeof rd);
         rd.N = c->N[r];
         rd.Np = (rd.N + 63) / 64 * 64;
+        rd.tpa = c->tpa_r[r];
         rd.base = (int32_t)slots;
         slots += rd.Np;
         rd.L = c->L[r];
@@ -1252,6 +1281,13 @@ int re_query_config(re_ctx* c, int* engine, int* threads_per_atom, int* team_siz
     if (engine) *engine = pers ? RE_PERSISTENT : RE_LOCKSTEP;
     if (threads_per_atom) *threads_per_atom = c->cfg.tpa;
     if (team_size) *team_size = c->pers_ok && !c->team_of.empty() ? c->team_of[0] : 0;
+    return RE_OK;
+}
+
+int re_query_lanes(re_ctx* c, int32_t* tpa)
+{
+    if (!c || !tpa) return fail(c, RE_EINVAL, "NULL argument");
+    for (int r = 0; r < c->R; ++r) tpa[r] = c->tpa_r[r];
     return RE_OK;
 }
 

@@ -38,6 +38,7 @@ struct RepDev {
     int32_t cell_base;  // first entry of this replica in the cell arrays (ncell^3 + 1 entries)
     int64_t nl_base;    // first element of this replica's neighbour list
     int32_t Np;         // N rounded up to a multiple of 64 (list row length)
+    int32_t tpa;        // lanes per atom of this replica's force pass and list layout (1, 2, 4, 8)
     float rlcell2;      // (list radius / cell side)^2 with a 1e-4 margin: row trimming
     double L;           // box side
     double s;           // length of one pair unit (mixed: L 2^-32; FP64: 1)
@@ -113,7 +114,7 @@ struct BlockTable {
 
 struct LaunchCfg {
     int block;      // threads per block of the wide kernels
-    int tpa;        // force-kernel lanes per atom
+    int tpa;        // force-kernel lanes per atom; 0: per replica (RepDev::tpa)
     int M;          // neighbour-list capacity per atom (a multiple of 32)
     int n16;        // mixed form: 16-bit list entries
     int64_t log_cap;
@@ -127,7 +128,7 @@ struct StepArgs {
     int r0;           // first replica (per-replica kernels)
     int blk_off;      // first block-table entry (wide kernels)
     int block;        // threads per block (wide kernels)
-    int tpa;          // force-kernel lanes per atom
+    int tpa;          // force-kernel lanes per atom; 0: per replica (RepDev::tpa)
     int M;            // neighbour-list capacity per atom (a multiple of 32)
     int n16;          // mixed form: 16-bit list entries (every replica <= 65536 atoms)
     int force_all;    // reorder/list: ignore the flags

@@ -293,13 +293,59 @@ __global__ __launch_bounds__(256) void k_listrows(DevState d, StepArgs sa, int n
         const int i = (vb - w.blk[k]) * kListAPB + (int)(threadIdx.x / kListLanes);
         const typename P::pos_t* pos = P::pos(d, sa.cur) + rd.base;
         list_rows<P, kListLanes>(d, rd, pos, pos, d.cell_start + rd.cell_base, i, i < rd.N, (int)(threadIdx.x % kListLanes),
-                                 sa.tpa, sa.M,
-                                 lds + threadIdx.x * W);
+                                 rd.tpa, sa.M, lds + threadIdx.x * W);
+    }
+}
+
+// Force + epilogue of one block of TPA-lane atom groups.  With TPA > 1 the
+// sums go through LDS and the step epilogues (noise, integration) then run
+// one atom per thread in the block's first blockDim/TPA threads, instead of
+// on one lane of each group while the others idle.
+template <class P, int MODE, int TPA>
+__device__ __forceinline__ void force_block(const DevState& d, const StepArgs& sa, const RepDev& rd, int r, int a0)
+{
+    const int tid = (int)threadIdx.x;
+    const int ia = a0 + tid / TPA;
+    if constexpr (TPA == 1) {
+        force_atom<P, MODE, TPA>(d, sa, rd, r, ia, 0, ia < rd.N, sa.cur, sa.step, sa.par);
+    } else {
+        using real = typename P::real;
+        using real4 = typename P::vel_t;
+        __shared__ real4 lf[256 / TPA];
+        __shared__ typename P::pos_t lp[256 / TPA];
+        typename P::pos_t pi;
+        real fx, fy, fz, e;
+        force_sum<P, MODE, TPA>(d, sa, rd, P::pos(d, sa.cur) + rd.base, ia, tid % TPA, ia < rd.N, pi, fx, fy, fz, e);
+        // this thread's epilogue atom; its velocity and x_ref are loaded
+        // before the barrier so that their latency overlaps it
+        const int ja = a0 + tid;
+        const bool epi = tid < (int)blockDim.x / TPA && ja < rd.N;
+        real4 v0{};
+        typename P::pos_t xr0{};
+        if (epi) {
+            if constexpr (MODE != kQuery) v0 = P::vel(d)[rd.base + ja];
+            if constexpr (MODE == kFused) xr0 = P::xref(d)[rd.base + ja];
+        }
+        if (tid % TPA == 0 && ia < rd.N) {
+            real4 f;
+            f.x = fx;
+            f.y = fy;
+            f.z = fz;
+            f.w = e;
+            lf[tid / TPA] = f;
+            lp[tid / TPA] = pi;
+        }
+        __syncthreads();
+        if (epi) {
+            const real4 f = lf[tid];
+            force_epilogue_v<P, MODE>(d, sa, rd, r, ja, sa.cur, sa.step, sa.par, lp[tid], f.x, f.y, f.z, f.w, v0, xr0);
+        }
     }
 }
 
 // Force + epilogue; the first block of each replica also marks the pending
-// velocity factor applied.
+// velocity factor applied.  TPA = 0: each block takes the lanes per atom of
+// its replica (a block table built with blockDim/tpa atoms per block).
 template <class P, int MODE, int TPA>
 __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
 {
@@ -309,8 +355,16 @@ __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
     const RepDev rd = d.rep[r];
     const int a0 = sa.tab.a0[b];
     if (MODE != kQuery && a0 == 0 && threadIdx.x == 0) d.alpha[r] = 1.0;
-    const int ia = a0 + (int)(threadIdx.x / TPA);
-    force_atom<P, MODE, TPA>(d, sa, rd, r, ia, (int)(threadIdx.x % TPA), ia < rd.N, sa.cur, sa.step, sa.par);
+    if constexpr (TPA != 0) {
+        force_block<P, MODE, TPA>(d, sa, rd, r, a0);
+    } else {
+        switch (rd.tpa) {
+        case 1: force_block<P, MODE, 1>(d, sa, rd, r, a0); break;
+        case 2: force_block<P, MODE, 2>(d, sa, rd, r, a0); break;
+        case 4: force_block<P, MODE, 4>(d, sa, rd, r, a0); break;
+        default: force_block<P, MODE, 8>(d, sa, rd, r, a0); break;
+        }
+    }
 }
 
 // Per-replica reductions at a stopped boundary: the potential energy
@@ -502,6 +556,7 @@ template <class P, int MODE>
 static hipError_t force_mode(const DevState& d, const StepArgs& sa, int nblk, hipStream_t st)
 {
     switch (sa.tpa) {
+    case 0: hipLaunchKernelGGL((k_force<P, MODE, 0>), dim3(nblk), dim3(sa.block), 0, st, d, sa); break;
     case 1: hipLaunchKernelGGL((k_force<P, MODE, 1>), dim3(nblk), dim3(sa.block), 0, st, d, sa); break;
     case 2: hipLaunchKernelGGL((k_force<P, MODE, 2>), dim3(nblk), dim3(sa.block), 0, st, d, sa); break;
     case 4: hipLaunchKernelGGL((k_force<P, MODE, 4>), dim3(nblk), dim3(sa.block), 0, st, d, sa); break;

@@ -530,7 +530,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                         bi = __shfl(bi, 0);
                         if (bi >= nbatch) break;
                         const int i = i0 + bi * kApw + (tid & 63) / kListLanes;
-                        list_rows<P, kListLanes>(d, rd, pos, keys, csp, i, i < i1, tid % kListLanes, pa.sa.tpa,
+                        list_rows<P, kListLanes>(d, rd, pos, keys, csp, i, i < i1, tid % kListLanes, rd.tpa,
                                                  pa.sa.M, cnt + tid * list_lds_words<kListLanes>());
                     }
                 };
@@ -565,13 +565,15 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             // to add; the stash of the force sums follows it.  The FP64 form
             // keeps the copy where the list build left its keys.)
             const typename P::pos_t* gpos = P::pos(d, cur) + rd.base;
-            const int apb = nt / TPA;
+            // lanes per atom: the kernel's, or (TPA = 0) this replica's
+            const int tpa_r = TPA ? TPA : rd.tpa;
+            const int apb = nt / tpa_r;
             constexpr int kPosAt = kKeyIsPos ? kTabWords : 0;
-            constexpr int kStashWords =
-                (int)((sizeof(typename P::vel_t) + sizeof(typename P::pos_t)) / sizeof(int)) * (1024 / TPA);
+            const int stash_words =
+                tpa_r == 1 ? 0 : (int)((sizeof(typename P::vel_t) + sizeof(typename P::pos_t)) / sizeof(int)) * (1024 / tpa_r);
             const int pos_words = (kPosWords * rd.N + 7) & ~7;  // (32-byte aligned stash)
             const bool lds_pos = kKeyIsPos ? kTabWords + kPosWords * rd.N <= kPersistLdsWords
-                                           : (TPA == 1 ? 0 : kStashWords) + pos_words <= kPersistLdsWords;
+                                           : stash_words + pos_words <= kPersistLdsWords;
             const int stash_at = kKeyIsPos || !lds_pos ? 0 : pos_words;
             typename P::pos_t* lpos = reinterpret_cast<typename P::pos_t*>(cnt + kPosAt);
             if (lds_pos && !staged) {
@@ -581,19 +583,20 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             // with TPA > 1 the sums of a pass go through LDS so that the
             // epilogues run one atom per thread (in the lanes of the atom's
             // group all but one would idle); LDS free between list builds
-            auto force_pass = [&](auto mode, const typename P::pos_t* fpos, int a0, int a1)
+            auto force_pass = [&](auto mode, auto lanes, const typename P::pos_t* fpos, int a0, int a1)
                                   __attribute__((always_inline)) {
                 constexpr int M = decltype(mode)::value;
+                constexpr int TL = decltype(lanes)::value;
                 using real = typename P::real;
                 using real4 = typename P::vel_t;
                 real4* lf = reinterpret_cast<real4*>(cnt + stash_at);
                 typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + apb);
                 for (int base = a0; base < a1; base += apb) {
-                    const int ia = base + tid / TPA;
+                    const int ia = base + tid / TL;
                     typename P::pos_t pi;
                     real fx, fy, fz, e;
-                    force_sum<P, M, TPA>(d, pa.sa, rd, fpos, ia, tid % TPA, ia < a1, pi, fx, fy, fz, e);
-                    if constexpr (TPA == 1) {
+                    force_sum<P, M, TL>(d, pa.sa, rd, fpos, ia, tid % TL, ia < a1, pi, fx, fy, fz, e);
+                    if constexpr (TL == 1) {
                         if (ia < a1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
                     } else {
                         // the velocity and x_ref of this thread's epilogue atom
@@ -607,14 +610,14 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                             if constexpr (M != kQuery) v0 = P::vel(d)[rd.base + ja];
                             if constexpr (M == kFused) xr0 = P::xref(d)[rd.base + ja];
                         }
-                        if (tid % TPA == 0 && ia < a1) {
+                        if (tid % TL == 0 && ia < a1) {
                             real4 f;
                             f.x = fx;
                             f.y = fy;
                             f.z = fz;
                             f.w = e;
-                            lf[tid / TPA] = f;
-                            lp[tid / TPA] = pi;
+                            lf[tid / TL] = f;
+                            lp[tid / TL] = pi;
                         }
                         __syncthreads();
                         if (epi) {
@@ -629,11 +632,23 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             static_assert(2 * 512 * sizeof(double4) <= sizeof(int) * kPersistLdsWords, "force stash exceeds LDS");
             // (separate calls for each position source, so that each inlined
             // copy knows its address space)
-            auto run = [&](auto mode) __attribute__((always_inline)) {
+            auto run_lanes = [&](auto mode, auto lanes) __attribute__((always_inline)) {
                 if (lds_pos)
-                    force_pass(mode, lpos, i0, i1);
+                    force_pass(mode, lanes, lpos, i0, i1);
                 else
-                    force_pass(mode, gpos, i0, i1);
+                    force_pass(mode, lanes, gpos, i0, i1);
+            };
+            auto run = [&](auto mode) __attribute__((always_inline)) {
+                if constexpr (TPA != 0) {
+                    run_lanes(mode, std::integral_constant<int, TPA>{});
+                } else {
+                    switch (rd.tpa) {
+                    case 1: run_lanes(mode, std::integral_constant<int, 1>{}); break;
+                    case 2: run_lanes(mode, std::integral_constant<int, 2>{}); break;
+                    case 4: run_lanes(mode, std::integral_constant<int, 4>{}); break;
+                    default: run_lanes(mode, std::integral_constant<int, 8>{}); break;
+                    }
+                }
             };
             if (!stop)
                 run(std::integral_constant<int, kFused>{});
@@ -738,6 +753,7 @@ template <class P, bool SVR>
 static hipError_t persist_t(const DevState& d, const PersistArgs& pa, int nblk, hipStream_t st)
 {
     switch (pa.sa.tpa) {
+    case 0: hipLaunchKernelGGL((k_persist<P, 0, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
     case 1: hipLaunchKernelGGL((k_persist<P, 1, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
     case 2: hipLaunchKernelGGL((k_persist<P, 2, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
     case 4: hipLaunchKernelGGL((k_persist<P, 4, SVR>), dim3(nblk), dim3(1024), 0, st, d, pa); break;
@@ -775,6 +791,7 @@ template <class P, bool SVR>
 static const void* persist_kernel(int tpa)
 {
     switch (tpa) {
+    case 0: return (const void*)k_persist<P, 0, SVR>;
     case 1: return (const void*)k_persist<P, 1, SVR>;
     case 2: return (const void*)k_persist<P, 2, SVR>;
     case 4: return (const void*)k_persist<P, 4, SVR>;

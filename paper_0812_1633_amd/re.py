@@ -40,7 +40,7 @@ class Options(C.Structure):
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
                 ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
                 ("team_barrier", C.c_int), ("svr_tau", C.c_double), ("exchange_max_distance", C.c_int),
-                ("debug_delay_us", C.c_int)]
+                ("debug_delay_us", C.c_int), ("threads_per_atom_per_replica", C.POINTER(C.c_int32))]
 
 
 class XLogRec(C.Structure):
@@ -84,6 +84,7 @@ def lib():
         L.re_test_normals.argtypes = [C.c_int, u64, vp, C.c_int, vp]
         L.re_profile.argtypes = [vp, C.c_int]
         L.re_query_config.argtypes = [vp, vp, vp, vp]
+        L.re_query_lanes.argtypes = [vp, vp]
         L.re_query_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.re_destroy.argtypes = [vp]
         L.re_destroy.restype = None
@@ -94,7 +95,7 @@ def lib():
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
                   "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count",
-                  "re_query_forces", "re_test_exchange_noalloc"):
+                  "re_query_forces", "re_test_exchange_noalloc", "re_query_lanes"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -130,13 +131,15 @@ class Engine:
     alternating nearest neighbours).
     debug_delay_us: test hook (persistent engine): workgroups pause for up to
     this many microseconds after team barriers (0: off).
+    threads_per_atom_per_replica: R force lane counts (1, 2, 4, 8), one per
+    replica (None: threads_per_atom for all).
     """
 
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
                  tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0,
-                 exchange_max_distance=1, debug_delay_us=0):
+                 exchange_max_distance=1, debug_delay_us=0, threads_per_atom_per_replica=None):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -166,6 +169,10 @@ class Engine:
         o.svr_tau = float(svr_tau)
         o.exchange_max_distance = int(exchange_max_distance)
         o.debug_delay_us = int(debug_delay_us)
+        self._tpa_r = None
+        if threads_per_atom_per_replica is not None:
+            self._tpa_r = np.ascontiguousarray(threads_per_atom_per_replica, np.int32)
+            o.threads_per_atom_per_replica = self._tpa_r.ctypes.data_as(C.POINTER(C.c_int32))
         ctx = C.c_void_p()
         rc = lib().re_create(C.byref(ctx), self.R, _ptr(N), _ptr(T), float(rho), float(r_c), float(skin),
                              float(dt), int(N_x), int(seed), C.byref(o))
@@ -262,6 +269,12 @@ class Engine:
         m = np.zeros(1, np.int32)
         _check(lib().re_query_config(self._ctx, _ptr(e), _ptr(t), _ptr(m)), self._ctx)
         return ("persistent" if e[0] == RE_PERSISTENT else "lockstep"), int(t[0]), int(m[0])
+
+    def query_lanes(self):
+        """Force lanes per atom of each replica."""
+        t = np.zeros(self.R, np.int32)
+        _check(lib().re_query_lanes(self._ctx, _ptr(t)), self._ctx)
+        return t
 
     def profile(self, enable):
         _check(lib().re_profile(self._ctx, int(enable)), self._ctx)

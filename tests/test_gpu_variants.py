@@ -261,3 +261,46 @@ def test_list_overflow_is_reported(relib, engine):
         e.step(1)
     assert err.value.code == relib.RE_EOVERFLOW
     e.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_lanes_per_replica(relib, precision):
+    """Replicas of four sizes, each with its own force lanes per atom (the
+    per-size-class choice the autotuner can make): the engines' force passes
+    (1e-5 / 1e-12) and 100-step trajectories against the oracle (FP64 1e-9;
+    mixed three of four within 1e-4, all within 1e-2: the spread of FP32
+    pair arithmetic through a chaotic trajectory with a truncated force),
+    and the two engines bitwise equal."""
+    N = [600, 1500, 3100, 4000]
+    tpa = [8, 4, 2, 1]
+    T = W.ladder(0.8, 1.4, 4)
+    rho, seed = 0.8442, 13
+    rc, skin, dt = PARAMS["c2"]
+    out = {}
+    for engine in ("lockstep", "persistent"):
+        e = relib.Engine(N, T, rho, rc, skin, dt, NOX, seed, precision=precision, engine=engine,
+                         threads_per_atom_per_replica=tpa, watchdog_seconds=10)
+        assert list(e.query_lanes()) == tpa
+        assert e.query_config()[:2] == (engine, 0)
+        L, xs, vs = injected(e, N, T, rho, 0.05, 300)
+        e.step(1)
+        ens = oracle_ensemble(N, L, T, rc, skin, dt, seed, xs, vs)
+        ens.run_sync(1, NOX)
+        tol = 1e-5 if precision == "mixed" else 1e-12
+        for r in range(4):
+            assert normwise(e.query_forces(r), replica_F(ens, r)) <= tol, (engine, r)
+        e.step(99)
+        ens.run_sync(99, NOX)
+        dev = np.array([mi_dist(e.get_state(r)[0], ens.replica_x(r), L[r]) for r in range(4)])
+        if precision == "fp64":
+            assert dev.max() <= 1e-9, (engine, dev)
+        else:
+            # (the mixed form's 100-step bar as read for several replicas of
+            # thousands of atoms: three quarters within 1e-4, all within 1e-2)
+            assert (dev <= 1e-4).sum() >= 3 and dev.max() <= 1e-2, (engine, dev)
+        out[engine] = [e.get_state(r) for r in range(4)] + [e.query_energies()]
+        e.close()
+    for r in range(4):
+        assert np.array_equal(out["lockstep"][r][0], out["persistent"][r][0])
+        assert np.array_equal(out["lockstep"][r][1], out["persistent"][r][1])
+    assert np.array_equal(out["lockstep"][4], out["persistent"][4])

@@ -58,7 +58,7 @@ def test_invalid_arguments(R, kw, msg):
 
 
 def test_invalid_options(R):
-    for kw in (dict(threads_per_atom=3), dict(block_size=100)):
+    for kw in (dict(threads_per_atom=3), dict(block_size=100), dict(threads_per_atom_per_replica=[6])):
         with pytest.raises(R.ReError) as e:
             R.Engine([256], [1.0], 0.8442, 2.5, 0.3, 0.005, 10, 1, **kw)
         assert e.value.code == R.RE_EINVAL
