@@ -129,6 +129,8 @@ def main():
     ap.add_argument("--workload", default="lj-32x4000")
     ap.add_argument("--engine", default=None, help="persistent | lockstep (default: autotuned)")
     ap.add_argument("--tpa", type=int, default=0, help="force lanes per atom with --engine (default: 4)")
+    ap.add_argument("--team-balance", action="store_true",
+                    help="persistent engine: re-plan teams from measured list-update rates")
     ap.add_argument("--melt-steps", type=int, default=500,
                     help="input preparation: steps at T = 1.5 from the FCC start (0: start from FCC)")
     ap.add_argument("--equil-steps", type=int, default=500,
@@ -167,7 +169,7 @@ def main():
     atoms = int(N.sum())
     Rn = len(N)
     kw = dict(rho_per_replica=rho, gamma=cfg["gamma"])
-    tune = {}
+    tune = {"team_balance": True} if args.team_balance else {}
     if args.engine:
         tune["engine"] = args.engine
         tune["threads_per_atom"] = args.tpa

@@ -141,6 +141,16 @@ typedef struct {
                                     for every replica.  With autotune, the
                                     tuner may set it per size class
                                     (floor(log2 N)); see re_query_lanes   */
+    int team_balance;            /* persistent engine with automatic team sizes:
+                                    nonzero re-plans the teams once every
+                                    replica has done 500 steps since the last
+                                    plan, weighting replica r by
+                                    N_r (1 + 4 u_r), u_r its list updates per
+                                    step in that window (hot replicas update
+                                    more often; with equal teams the others
+                                    wait for them at synchronous exchanges);
+                                    results do not depend on the teams.
+                                    0 (default): teams proportional to N */
 } re_options;
 
 /* One record per ladder pair per exchange attempt. */
@@ -310,6 +320,10 @@ int re_query_config(re_ctx* ctx, int* engine, int* threads_per_atom, int* team_s
 
 /* Force lanes per atom of each replica (R values). */
 int re_query_lanes(re_ctx* ctx, int32_t* tpa);
+
+/* Persistent engine: workgroups serving each replica in the current plan
+ * (R values; 0 when the persistent engine is not available). */
+int re_query_teams(re_ctx* ctx, int32_t* team);
 
 /* Free everything owned by the context (NULL is allowed). */
 void re_destroy(re_ctx* ctx);

@@ -73,6 +73,7 @@ struct re_ctx {
     // i64), steps per replica (R x i64); h_stat is its pinned host copy
     unsigned char* d_stat = nullptr;
     unsigned char* h_stat = nullptr;
+    bool stat_valid = false;       // h_stat holds the state after the last persistent call
     std::vector<void*> pinned;     // pinned host allocations
     int64_t* d_sched = nullptr;
     int64_t sched_cap = 0;
@@ -82,6 +83,10 @@ struct re_ctx {
     unsigned* bar = nullptr;
     int pnblk = 0, pnteams = 0;
     std::vector<int> team_of;    // team size chosen per replica
+    int team_opt = 0;            // explicit team size (0: automatic)
+    bool balance = false;        // rebalance automatic teams from measured list-update rates
+    std::vector<int64_t> plan_steps, plan_reb;  // steps and list updates at the last plan
+    int rebalanced = 0;          // plans that changed a team since creation
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     int bar_mode = 0;            // team barrier mode of the persistent engine
@@ -488,11 +493,18 @@ static int d2h(re_ctx* c, T* dst, const T* src, size_t n)
 // ---------------------------------------------------------------------------
 // Persistent engine: team planning.  One 1024-thread workgroup per CU can be
 // resident (the reorder's cell counts fill most of the LDS), so at most
-// #CUs workgroups run.  Replica r gets a team of t_r workgroups in
-// proportion to its atoms (at least one, at most one per 256 atoms); a
-// team's workgroups are placed on one XCD when it fits (block ids of one
-// residue mod 8 go to the same XCD), so the replica's data stays in one L2.
-static int plan_persistent(re_ctx* c, int team_opt)
+// #CUs workgroups run; block ids of one residue mod 8 go to the same XCD.
+// Replica r gets a team of t_r workgroups (at least one, at most one per
+// 256 atoms) in proportion to its weight w_r: its atoms, or its atoms times
+// the cost of its measured step (list updates included) when the teams are
+// rebalanced.  With at least 8 replicas every team stays on one XCD, so
+// that a replica's data stays in one L2 and its barrier needs no L2
+// write-back: the replicas are dealt to the XCDs largest weight first,
+// each to the XCD with the least weight so far (at most ceil(R/8) each),
+// and each XCD's CUs are split among its replicas by weight.  With fewer
+// replicas (or an explicit team size) the teams are sized over the whole
+// device and placed largest first, on one XCD where they fit.
+static int plan_persistent(re_ctx* c, int team_opt, const std::vector<double>* weight = nullptr)
 {
     int dev = 0, cus = 0, occ = 0;
     HIPCHK(c, hipGetDevice(&dev));
@@ -506,43 +518,104 @@ static int plan_persistent(re_ctx* c, int team_opt)
                       " available, " + std::to_string(R) + " replicas)";
         return 0;
     }
-    std::vector<int> t(R, 1);
-    if (team_opt > 0) {
-        for (int r = 0; r < R; ++r) t[r] = team_opt;
-    } else {
-        double tot = 0;
-        for (int r = 0; r < R; ++r) tot += c->N[r];
-        for (int r = 0; r < R; ++r) t[r] = std::max(1, (int)std::floor(cap * c->N[r] / tot));
-    }
-    for (int r = 0; r < R; ++r) t[r] = std::max(1, std::min(t[r], (c->N[r] + 255) / 256));
-    for (;;) {
-        int sum = 0, big = 0;
-        for (int r = 0; r < R; ++r) {
-            sum += t[r];
-            if (t[r] > t[big]) big = r;
-        }
-        if (sum <= cap) break;
-        t[big] -= 1;
-    }
-    // place teams: largest first, onto the XCD with the most free slots
+    std::vector<double> w(R);
+    for (int r = 0; r < R; ++r) w[r] = weight ? (*weight)[r] : (double)c->N[r];
     const int X = 8, per = (cap + X - 1) / X;
-    std::vector<int> freec(X, per), order(R);
-    for (int r = 0; r < R; ++r) order[r] = r;
-    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] > t[b]; });
+    auto tcap = [&](int r) { return std::max(1, (c->N[r] + 255) / 256); };
     std::vector<int32_t> brep(X * per, -1), bmem(X * per, 0), bsize(X * per, 1), bid(X * per, 0);
-    std::vector<int> used(X, 0);
-    for (int k = 0; k < R; ++k) {
-        const int r = order[k];
-        int x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
-        for (int m = 0; m < t[r]; ++m) {
-            if (freec[x] == 0) x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
-            const int b = x + X * used[x];
-            used[x] += 1;
-            freec[x] -= 1;
-            brep[b] = r;
-            bmem[b] = m;
-            bsize[b] = t[r];
-            bid[b] = r;
+    std::vector<int> t(R, 1);
+    if (team_opt <= 0 && R >= X && cap % X == 0) {
+        // deal the replicas to the XCDs, then split each XCD's CUs
+        std::vector<int> order(R), xof(R);
+        for (int r = 0; r < R; ++r) order[r] = r;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+        const int maxper = (R + X - 1) / X;
+        std::vector<double> wx(X, 0.0);
+        std::vector<std::vector<int>> members(X);
+        for (int r : order) {
+            int best = -1;
+            for (int x = 0; x < X; ++x)
+                if ((int)members[x].size() < maxper && (best < 0 || wx[x] < wx[best])) best = x;
+            members[best].push_back(r);
+            wx[best] += w[r];
+            xof[r] = best;
+        }
+        for (int x = 0; x < X; ++x) {
+            auto& m = members[x];
+            if (m.empty()) continue;
+            int used = 0;
+            for (int r : m) {
+                t[r] = std::max(1, std::min(tcap(r), (int)std::floor(per * w[r] / wx[x])));
+                used += t[r];
+            }
+            // the XCD's remaining CUs, one at a time, to the heaviest replica
+            // per workgroup that can still grow
+            while (used < per) {
+                int pick = -1;
+                for (int r : m)
+                    if (t[r] < tcap(r) && (pick < 0 || w[r] / t[r] > w[pick] / t[pick])) pick = r;
+                if (pick < 0) break;
+                t[pick] += 1;
+                used += 1;
+            }
+            while (used > per) {  // (only when there are more replicas than CUs here)
+                int pick = -1;
+                for (int r : m)
+                    if (t[r] > 1 && (pick < 0 || w[r] / t[r] < w[pick] / t[pick])) pick = r;
+                if (pick < 0) break;
+                t[pick] -= 1;
+                used -= 1;
+            }
+            int k = 0;
+            for (int r : m)
+                for (int mm = 0; mm < t[r]; ++mm, ++k) {
+                    const int b = x + X * k;
+                    brep[b] = r;
+                    bmem[b] = mm;
+                    bsize[b] = t[r];
+                    bid[b] = r;
+                }
+            if (k > per) {
+                c->pers_why = "team placement exceeds the resident workgroups of an XCD";
+                return 0;
+            }
+        }
+    } else {
+        if (team_opt > 0) {
+            for (int r = 0; r < R; ++r) t[r] = team_opt;
+        } else {
+            double tot = 0;
+            for (int r = 0; r < R; ++r) tot += w[r];
+            for (int r = 0; r < R; ++r) t[r] = std::max(1, (int)std::floor(cap * w[r] / tot));
+        }
+        for (int r = 0; r < R; ++r) t[r] = std::max(1, std::min(t[r], tcap(r)));
+        for (;;) {
+            int sum = 0, big = 0;
+            for (int r = 0; r < R; ++r) {
+                sum += t[r];
+                if (t[r] > t[big]) big = r;
+            }
+            if (sum <= cap) break;
+            t[big] -= 1;
+        }
+        // place teams: largest first, onto the XCD with the most free slots
+        std::vector<int> freec(X, per), order(R);
+        for (int r = 0; r < R; ++r) order[r] = r;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return t[a] > t[b]; });
+        std::vector<int> used(X, 0);
+        for (int k = 0; k < R; ++k) {
+            const int r = order[k];
+            int x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
+            for (int m = 0; m < t[r]; ++m) {
+                if (freec[x] == 0) x = (int)(std::max_element(freec.begin(), freec.end()) - freec.begin());
+                const int b = x + X * used[x];
+                used[x] += 1;
+                freec[x] -= 1;
+                brep[b] = r;
+                bmem[b] = m;
+                bsize[b] = t[r];
+                bid[b] = r;
+            }
         }
     }
     int nblk = 0;
@@ -576,6 +649,45 @@ static int plan_persistent(re_ctx* c, int team_opt)
     return 0;
 }
 
+// Rebalancing of the teams from the measured list-update rates (persistent
+// engine, automatic team sizes): once every replica has done kBalanceSteps
+// steps since the last plan, replica r is weighted by N_r (1 + kListCost u_r),
+// u_r its list updates per step in that window and kListCost the cost of
+// one update (reorder, list build and their barriers) in units of one
+// step's force phase, about 4 at 4000 atoms per replica.  The teams are
+// re-planned (and the launch graph re-captured) when a team changes size.
+// Hot replicas update their lists about twice as often as cold ones, so
+// with equal teams the cold ones wait for them at every synchronous
+// exchange.  Results do not depend on the teams.
+constexpr int64_t kBalanceSteps = 500;
+constexpr double kListCost = 4.0;
+
+static int maybe_rebalance(re_ctx* c, const int64_t* steps)
+{
+    const int R = c->R;
+    if (!c->balance || c->team_opt > 0 || c->plan_steps.empty()) return 0;
+    int64_t dmin = INT64_MAX;
+    for (int r = 0; r < R; ++r) dmin = std::min(dmin, steps[r] - c->plan_steps[r]);
+    if (dmin < kBalanceSteps) return 0;
+    std::vector<int64_t> reb(R);
+    int rc = d2h(c, reb.data(), c->d.rebuilds, R);
+    if (rc) return rc;
+    std::vector<double> w(R);
+    for (int r = 0; r < R; ++r) {
+        const double u = (double)(reb[r] - c->plan_reb[r]) / (double)std::max<int64_t>(1, steps[r] - c->plan_steps[r]);
+        w[r] = (double)c->N[r] * (1.0 + kListCost * u);
+    }
+    c->plan_steps.assign(steps, steps + R);
+    c->plan_reb = reb;
+    const std::vector<int> before = c->team_of;
+    if ((rc = plan_persistent(c, 0, &w))) return rc;
+    if (!c->pers_ok) {  // (cannot happen for a plan that fitted before; keep the old one)
+        return plan_persistent(c, 0, nullptr);
+    }
+    c->rebalanced += c->team_of != before ? 1 : 0;
+    return 0;
+}
+
 static PersistArgs persist_args(re_ctx* c)
 {
     PersistArgs pa{};
@@ -605,6 +717,13 @@ static int run_persistent(re_ctx* c, int64_t n)
     if (!c->pers_ok) return fail(c, RE_ESTATE, "%s", c->pers_why.c_str());
     const int R = c->R;
     int rc;
+    // teams rebalanced from the list-update rates measured so far (the step
+    // counts are those the previous call read back)
+    {
+        const int64_t* st = reinterpret_cast<const int64_t*>(c->h_stat + 8) + R;
+        if (c->stat_valid && (rc = maybe_rebalance(c, st))) return rc;
+        if (!c->pers_ok) return fail(c, RE_ESTATE, "%s", c->pers_why.c_str());
+    }
     // per-call parameters through pinned memory: the copy is queued and the
     // host goes on; every call ends with a synchronisation, so the staging
     // buffer is free again when the next call writes it
@@ -666,6 +785,7 @@ static int run_persistent(re_ctx* c, int64_t n)
     const int64_t* steps = katt + R;
     c->next_attempt = *std::max_element(katt, katt + R);
     c->step = steps[0];
+    c->stat_valid = true;
     c->sched.clear();
     c->sched_A = 0;
     if (err & kErrTimeout)
@@ -933,8 +1053,16 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
     ALLOC(d.cell_start, cells);
     {
         unsigned char* nlp = nullptr;
-        ALLOC(nlp, (nl + (int64_t)kListSlackRows * 8 * ((c->nmax + 63) / 64 * 64)) * esz);
+        const size_t nl_bytes_all = (size_t)((nl + (int64_t)kListSlackRows * 8 * ((c->nmax + 63) / 64 * 64)) * esz);
+        ALLOC(nlp, nl_bytes_all);
         d.nl = nlp;
+        // zeroed: every entry of a replica's block then names one of its
+        // atoms (slot 0) until a list build writes it, so the force loops'
+        // reads past an atom's rows stay inside the replica
+        if (hipMemset(nlp, 0, nl_bytes_all) != hipSuccess) {
+            c->err = "hipMemset of the neighbour lists failed";
+            return bail(RE_EDEVICE);
+        }
     }
     ALLOC(d.nn, slots);
     ALLOC(d.rep, R);
@@ -1043,7 +1171,17 @@ int re_create(re_ctx** out, int R, const int32_t* N_atoms, const double* T_ladde
         }
     }
     if ((rc = refresh_replicas(c, 0, R)) || (rc = check_overflow(c))) return bail(rc);
+    c->team_opt = o.team_size;
+    c->balance = o.team_balance != 0;
     if (c->form == RE_BATCHED && (rc = plan_persistent(c, o.team_size))) return bail(rc);
+    if (c->form == RE_BATCHED && c->pers_ok) {
+        // the first window of the team rebalancing starts here
+        std::memset(c->h_stat, 0, 8 + 16 * (size_t)R);
+        c->stat_valid = true;
+        c->plan_steps.assign(R, 0);
+        c->plan_reb.assign(R, 0);
+        if ((rc = d2h(c, c->plan_reb.data(), c->d.rebuilds, R))) return bail(rc);
+    }
     if (c->xmode == RE_ASYNC && !c->pers_ok) {
         c->err = "asynchronous exchange needs the persistent engine: " + c->pers_why;
         return bail(RE_EINVAL);
@@ -1281,6 +1419,22 @@ int re_query_config(re_ctx* c, int* engine, int* threads_per_atom, int* team_siz
     if (engine) *engine = pers ? RE_PERSISTENT : RE_LOCKSTEP;
     if (threads_per_atom) *threads_per_atom = c->cfg.tpa;
     if (team_size) *team_size = c->pers_ok && !c->team_of.empty() ? c->team_of[0] : 0;
+    return RE_OK;
+}
+
+#ifdef RE_PHASE_TIMERS
+// (instrumented build) the replica served by each workgroup of the launch
+extern "C" int re_debug_team_rep(re_ctx* c, int32_t* out, int nmax)
+{
+    if (!c || !out || nmax < c->pnblk) return -1;
+    return hipMemcpy(out, c->t_rep, (size_t)c->pnblk * 4, hipMemcpyDeviceToHost) == hipSuccess ? c->pnblk : -3;
+}
+#endif
+
+int re_query_teams(re_ctx* c, int32_t* team)
+{
+    if (!c || !team) return fail(c, RE_EINVAL, "NULL argument");
+    for (int r = 0; r < c->R; ++r) team[r] = c->pers_ok && (int)c->team_of.size() == c->R ? c->team_of[r] : 0;
     return RE_OK;
 }
 

@@ -47,7 +47,9 @@ __device__ __forceinline__ uint64_t clock100()
 // workgroup adds the 100 MHz ticks spent in each phase of k_persist to its
 // own row; re_debug_phase_ticks copies the rows out and clears them.
 #ifdef RE_PHASE_TIMERS
-constexpr int kPhases = 8;
+// phases 0..7 of the step loop; 8, 9: inside the exchange join, the wait
+// at the gate and the wait for the partner's post
+constexpr int kPhases = 12;
 __device__ unsigned long long g_phase_ticks[1024 * kPhases];
 #define PT_INIT() uint64_t pt_last = clock100()
 #define PT_MARK(k)                                                  \
@@ -199,7 +201,13 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
     const int R = pa.sa.R;
     const int p = (int)(k & 1);
     if (threadIdx.x == 0) {
+#ifdef RE_PHASE_TIMERS
+        const uint64_t tg0 = clock100();
+#endif
         int ok = wait_ge_u64(pa, ps.xdone, (uint64_t)R * (uint64_t)(k - cp.k0)) ? 1 : 0;
+#ifdef RE_PHASE_TIMERS
+        g_phase_ticks[blockIdx.x * kPhases + 8] += clock100() - tg0;
+#endif
         if (ok && cp.mode == kModeAsync && (int)(k % R) == r) {
             // the master publishes the trigger of attempt k
             __hip_atomic_fetch_max(ps.trig, (uint64_t)(k + 1), __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
@@ -234,7 +242,13 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
         __hip_atomic_store(ps.post + r, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int newslot = jme;
         if (q >= 0) {
+#ifdef RE_PHASE_TIMERS
+            const uint64_t tp0 = clock100();
+#endif
             ok = wait_ge_i64(pa, ps.post + q, k + 1) ? 1 : 0;
+#ifdef RE_PHASE_TIMERS
+            g_phase_ticks[blockIdx.x * kPhases + 9] += clock100() - tp0;
+#endif
             if (ok) {
                 const double Uq = ps.upost[(size_t)p * R + q];
                 const int64_t sq = ps.spost[(size_t)p * R + q];

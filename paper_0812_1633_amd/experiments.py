@@ -8,6 +8,12 @@
 * ``diffusion``: diffusion coefficient D of log T against the observed
   exchange stride <N_x> (Diffusion subsection, Fig. 1a), for both forms at
   N_r = 48.
+* ``acceptance``: the acceptance of each ladder pair against the estimate
+  from the run's own energy distributions (Gaussian energies), and the
+  configurational heat capacity along the ladder, which sets the acceptance
+  the Example section reports for its ladder ratio.
+* ``phases``: where the persistent kernel's time goes per step, without and
+  with exchanges (a library built with the phase timers).
 
 The workload is the paper's Lennard-Jones liquid: 4000 atoms per replica at
 density 0.844, cutoff 2.5, neighbour list to 3.0 (skin 0.5) updated at half
@@ -192,9 +198,159 @@ def diffusion(Nr=48, sync_Nx=(2, 5, 10, 20, 50), async_Nx=(1, 2, 5, 10, 20), ste
     return dict(experiment="diffusion", workload=dict(PAPER, N=N), Nr=Nr, steps=steps, warmup=warmup, rows=rows)
 
 
+# ---------------------------------------------------------------------------
+# Acceptance along the ladder against the Gaussian-energy estimate
+
+def expected_min1_exp(m, v):
+    """E[min(1, e^x)] for x ~ N(m, v): P(x >= 0) + E[e^x; x < 0]."""
+    from math import erfc, exp, sqrt
+    sd = sqrt(v)
+    phi = lambda z: 0.5 * erfc(-z / sqrt(2.0))
+    return phi(m / sd) + exp(m + 0.5 * v) * phi(-(m + v) / sd)
+
+
+def ladder_acceptance(log, T_ladder, kmin=0):
+    """Per ladder pair (j, j+1): the measured acceptance of the records of
+    attempts >= kmin, and the estimate from the energies the log holds.
+    Every record gives the energy of the replica at slot j (U_a, at T_a) and
+    at slot j+1 (U_b, at T_b); with the mean and variance of U at each
+    temperature, the Metropolis exponent (1/T_j - 1/T_{j+1})(U_a - U_b) of
+    two independent replicas is Gaussian with mean dB (mean_j - mean_{j+1})
+    and variance dB^2 (var_j + var_{j+1}), whose expected min(1, e^x) is the
+    estimate.  Also the configurational heat capacity per replica var / T^2
+    at each temperature."""
+    T = np.asarray(T_ladder, np.float64)
+    R = T.size
+    samples = [[] for _ in range(R)]
+    acc = [[] for _ in range(R - 1)]
+    for g in log:
+        if g.attempt < kmin:
+            continue
+        samples[g.slot_lo].append(g.U_a)
+        samples[g.slot_hi].append(g.U_b)
+        if g.slot_hi == g.slot_lo + 1:
+            acc[g.slot_lo].append(g.accepted)
+    mean = np.array([np.mean(x) if x else np.nan for x in samples])
+    var = np.array([np.var(x, ddof=1) if len(x) > 1 else np.nan for x in samples])
+    rows = []
+    for j in range(R - 1):
+        dB = 1.0 / T[j] - 1.0 / T[j + 1]
+        m = dB * (mean[j] - mean[j + 1])
+        v = dB * dB * (var[j] + var[j + 1])
+        est = expected_min1_exp(m, v) if np.isfinite(m) and v > 0 else None
+        rows.append(dict(j=j, T=float(T[j]), attempts=len(acc[j]),
+                         measured=float(np.mean(acc[j])) if acc[j] else None, gaussian=est,
+                         cv_conf=float(var[j] / T[j] ** 2) if np.isfinite(var[j]) else None))
+    return rows
+
+
+def acceptance(Nr=48, Nx=5, steps=20000, warmup=2000, N=PAPER["N"], seed=1):
+    """The paper's workload at N_r replicas, synchronous exchanges every N_x
+    steps: per ladder pair the measured acceptance against the
+    Gaussian-energy estimate from the run's own energies, and the
+    configurational heat capacity per atom along the ladder."""
+    from . import re as R
+    e = _engine(R, Nr, "sync", Nx, seed, N, log_capacity=1 << 22)
+    try:
+        e.step(warmup)
+        k0 = e.query_attempt_count()
+        e.step(steps)
+        log, _ = e.query_exchange_log()
+    finally:
+        e.close()
+    rows = ladder_acceptance(log, paper_ladder(Nr), k0)
+    meas = [r["measured"] for r in rows if r["measured"] is not None]
+    est = [r["gaussian"] for r in rows if r["gaussian"] is not None]
+    cv = [r["cv_conf"] / N for r in rows if r["cv_conf"] is not None]
+    return dict(experiment="acceptance", workload=dict(PAPER, N=N), Nr=Nr, Nx=Nx, steps=steps, warmup=warmup,
+                mean_measured=float(np.mean(meas)), mean_gaussian=float(np.mean(est)),
+                cv_conf_per_atom=dict(first=cv[0], last=cv[-1], mean=float(np.mean(cv))), rows=rows)
+
+
+# ---------------------------------------------------------------------------
+# Where the persistent kernel's time goes (instrumented build)
+
+PHASES = ("boundary, exchange join, barrier", "first half of a step, barrier", "reorder, barrier", "list build",
+          "force pass (the workgroup's first wave)", "team barrier after the forces",
+          "energy / rescale reductions at a stop (leader)", "rest of the workgroup after the force pass",
+          "exchange join: wait at the gate", "exchange join: wait for the partner")
+
+
+def _workload_engine(R, name, melt=500, equil=500, **kw):
+    """A persistent-engine context of a named benchmark workload, prepared as
+    the benchmark prepares it: every replica melted at T = 1.5 from the FCC
+    start, then equilibrated at its ladder temperature."""
+    from . import workloads as W
+    cfg = W.expand(name)
+    N, rho, T = cfg["N_list"], cfg["rho_list"], cfg["T_list"]
+    common = dict(rho_per_replica=rho, gamma=cfg["gamma"])
+    em = R.Engine(N, 1.5 * (1.0 + 1e-9 * np.arange(len(N))), 0.0, cfg["rc"], cfg["skin"], cfg["dt"], 10**9,
+                  cfg["seed"] + 1000, **common)
+    em.step(melt)
+    states = [em.get_state(r) for r in range(len(N))]
+    em.close()
+    e = R.Engine(N, T, 0.0, cfg["rc"], cfg["skin"], cfg["dt"], cfg["Nx"], cfg["seed"], engine="persistent",
+                 **common, **kw)
+    for r, (x, v) in enumerate(states):
+        e.set_state(r, x, v)
+    e.step(equil)
+    return e
+
+
+def phases(lib_path, Nr=16, modes=(("async", None), ("async", 1), ("sync", 5)), steps=1000, warmup=300,
+           N=PAPER["N"], seed=1, workload=None, threads_per_atom=2):
+    """Microseconds per step (and per workgroup) in each phase of the
+    persistent kernel, from a library built with RE_PHASE_TIMERS
+    (``paper_0812_1633_amd.build.build(defines=("RE_PHASE_TIMERS",),
+    lib_path=...)``): on the paper's workload at N_r replicas without
+    exchanges and with the given (mode, N_x); or, with ``workload``, on that
+    benchmark workload (its own exchange settings, melted start).  The last
+    two phases lie inside the first."""
+    import ctypes as C
+    from . import re as R
+    R.LIB_PATH = lib_path
+    L = R.lib()
+    L.re_debug_phase_ticks.argtypes = [C.c_void_p, C.c_int]
+    rows = []
+    buf = np.zeros(1024 * 12, np.uint64)
+    if workload:
+        modes = (("workload", None),)
+    for mode, nx in modes:
+        if workload:
+            e = _workload_engine(R, workload, threads_per_atom=threads_per_atom)
+            Nr = e.R
+        else:
+            e = _engine(R, Nr, mode, nx or 10**9, seed, N, log_capacity=1 << 16)
+        try:
+            e.step(warmup)
+            L.re_debug_phase_ticks(buf.ctypes.data, 1024)
+            s0, _ = e.query_steps()
+            a0 = e.query_attempt_count()
+            t0 = time.perf_counter()
+            e.step(steps)
+            t1 = time.perf_counter()
+            s1, _ = e.query_steps()
+            a1 = e.query_attempt_count()
+            L.re_debug_phase_ticks(buf.ctypes.data, 1024)
+        finally:
+            e.close()
+        t = buf.reshape(1024, 12).astype(np.float64)
+        act = t[:, :8].sum(1) > 0
+        done = float((s1 - s0).sum())
+        us = t[act].mean(0)[:len(PHASES)] / 100.0 / (done / Nr)  # 100 MHz ticks
+        rows.append(dict(mode=mode, Nx=nx, steps_per_s_per_replica=done / Nr / (t1 - t0),
+                         mean_Nx=(done / (Nr * (a1 - a0))) if a1 > a0 else None,
+                         us_per_step=dict(zip(PHASES, [float(x) for x in us]))))
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    return dict(experiment="phases", workload=workload or dict(PAPER, N=N), Nr=Nr, steps=steps, warmup=warmup,
+                rows=rows)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("which", choices=["efficiency", "diffusion"])
+    ap.add_argument("which", choices=["efficiency", "diffusion", "acceptance", "phases"])
+    ap.add_argument("--lib", default=None, help="phases: a library built with RE_PHASE_TIMERS")
+    ap.add_argument("--workload", default=None, help="phases: a benchmark workload instead of the paper's")
     ap.add_argument("--out", default=None)
     ap.add_argument("--steps", type=int, default=None)
     ap.add_argument("--warmup", type=int, default=None)
@@ -210,6 +366,17 @@ def main(argv=None):
         if args.replicas:
             kw["Nr_list"] = tuple(int(x) for x in args.replicas.split(","))
         res = efficiency(**kw)
+    elif args.which == "phases":
+        if args.replicas:
+            kw["Nr"] = int(args.replicas)
+        if args.workload:
+            kw["workload"] = args.workload
+            kw.pop("N", None)
+        res = phases(args.lib, **kw)
+    elif args.which == "acceptance":
+        if args.replicas:
+            kw["Nr"] = int(args.replicas)
+        res = acceptance(**kw)
     else:
         res = diffusion(**kw)
     txt = json.dumps(res, indent=1)

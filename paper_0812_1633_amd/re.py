@@ -40,7 +40,8 @@ class Options(C.Structure):
                 ("log_capacity", C.c_int64), ("threads_per_atom", C.c_int), ("block_size", C.c_int),
                 ("team_size", C.c_int), ("tune_cache", C.c_char_p), ("autotune", C.c_int),
                 ("team_barrier", C.c_int), ("svr_tau", C.c_double), ("exchange_max_distance", C.c_int),
-                ("debug_delay_us", C.c_int), ("threads_per_atom_per_replica", C.POINTER(C.c_int32))]
+                ("debug_delay_us", C.c_int), ("threads_per_atom_per_replica", C.POINTER(C.c_int32)),
+                ("team_balance", C.c_int)]
 
 
 class XLogRec(C.Structure):
@@ -85,6 +86,7 @@ def lib():
         L.re_profile.argtypes = [vp, C.c_int]
         L.re_query_config.argtypes = [vp, vp, vp, vp]
         L.re_query_lanes.argtypes = [vp, vp]
+        L.re_query_teams.argtypes = [vp, vp]
         L.re_query_kernel_time.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
         L.re_destroy.argtypes = [vp]
         L.re_destroy.restype = None
@@ -95,7 +97,7 @@ def lib():
                   "re_query_exchange_log", "re_get_state", "re_set_state", "re_compute_forces",
                   "re_set_schedule", "re_test_exchange", "re_test_philox", "re_test_normals",
                   "re_profile", "re_query_kernel_time", "re_query_config", "re_query_attempt_count",
-                  "re_query_forces", "re_test_exchange_noalloc", "re_query_lanes"):
+                  "re_query_forces", "re_test_exchange_noalloc", "re_query_lanes", "re_query_teams"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -133,13 +135,17 @@ class Engine:
     this many microseconds after team barriers (0: off).
     threads_per_atom_per_replica: R force lane counts (1, 2, 4, 8), one per
     replica (None: threads_per_atom for all).
+    team_balance: persistent engine, automatic team sizes: re-plan the teams
+    from the measured list-update rates (off by default: teams proportional
+    to N).
     """
 
     def __init__(self, N, T_ladder, rho, r_c, skin, dt, N_x, seed, *, gamma=None, precision="mixed",
                  form="batched", engine="persistent", exchange="sync", rho_per_replica=None, stream=None,
                  watchdog_seconds=0.0, log_capacity=0, threads_per_atom=0, block_size=0, team_size=0,
                  tune_cache=None, autotune=False, team_barrier="auto", thermostat="langevin", svr_tau=0.0,
-                 exchange_max_distance=1, debug_delay_us=0, threads_per_atom_per_replica=None):
+                 exchange_max_distance=1, debug_delay_us=0, threads_per_atom_per_replica=None,
+                 team_balance=False):
         self._ctx = None
         N = np.ascontiguousarray(N, np.int32)
         T = np.ascontiguousarray(T_ladder, np.float64)
@@ -169,6 +175,7 @@ class Engine:
         o.svr_tau = float(svr_tau)
         o.exchange_max_distance = int(exchange_max_distance)
         o.debug_delay_us = int(debug_delay_us)
+        o.team_balance = 1 if team_balance else 0
         self._tpa_r = None
         if threads_per_atom_per_replica is not None:
             self._tpa_r = np.ascontiguousarray(threads_per_atom_per_replica, np.int32)
@@ -274,6 +281,12 @@ class Engine:
         """Force lanes per atom of each replica."""
         t = np.zeros(self.R, np.int32)
         _check(lib().re_query_lanes(self._ctx, _ptr(t)), self._ctx)
+        return t
+
+    def query_teams(self):
+        """Persistent engine: workgroups serving each replica."""
+        t = np.zeros(self.R, np.int32)
+        _check(lib().re_query_teams(self._ctx, _ptr(t)), self._ctx)
         return t
 
     def profile(self, enable):

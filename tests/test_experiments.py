@@ -51,3 +51,43 @@ def test_diffusion_estimator_recovers_known_D(p, stride):
     assert D == pytest.approx(D_true, rel=0.06)
     # the MSD itself is linear with the closed-form slope
     assert np.allclose(m, p * delta ** 2 * lags / stride, rtol=0.08)
+
+
+def test_expected_min1_exp_closed_form():
+    """E[min(1, e^x)] for Gaussian x against Monte Carlo, and the
+    detailed-balance case m = -v/2, where it equals erfc(sqrt(v) / (2 sqrt 2))."""
+    import math
+    from paper_0812_1633_amd import experiments as E
+    g = np.random.default_rng(0)
+    for m, v in ((-0.3, 0.6), (0.2, 0.1), (-2.0, 1.5), (-0.05, 0.1)):
+        x = g.normal(m, np.sqrt(v), 400000)
+        mc = np.minimum(1.0, np.exp(x)).mean()
+        assert E.expected_min1_exp(m, v) == pytest.approx(mc, abs=3e-3)
+    for v in (0.1, 1.0, 4.0):
+        assert E.expected_min1_exp(-v / 2, v) == pytest.approx(math.erfc(math.sqrt(v) / (2 * math.sqrt(2))), rel=1e-12)
+
+
+def test_ladder_acceptance_on_synthetic_log():
+    """Synthetic exchange records with Gaussian energies of known mean and
+    variance per temperature: the per-pair estimate matches the closed form
+    and the measured rate is the records' mean."""
+    from types import SimpleNamespace
+    from paper_0812_1633_amd import experiments as E
+    T = np.array([1.0, 1.05, 1.1, 1.16])
+    mu = -5000.0 + 900.0 * (T - 1.0) * 10
+    sd = np.sqrt(1.0 * T ** 2 * 400.0)
+    g = np.random.default_rng(1)
+    recs = []
+    for k in range(40000):
+        j0 = k % 2
+        for j in range(j0, len(T) - 1, 2):
+            ua, ub = g.normal(mu[j], sd[j]), g.normal(mu[j + 1], sd[j + 1])
+            recs.append(SimpleNamespace(attempt=k, slot_lo=j, slot_hi=j + 1, U_a=ua, U_b=ub, accepted=int(k % 3 == 0)))
+    rows = E.ladder_acceptance(recs, T, 0)
+    for r in rows:
+        j = r["j"]
+        dB = 1 / T[j] - 1 / T[j + 1]
+        expect = E.expected_min1_exp(dB * (mu[j] - mu[j + 1]), dB * dB * (sd[j] ** 2 + sd[j + 1] ** 2))
+        assert r["gaussian"] == pytest.approx(expect, abs=0.01)
+        assert r["measured"] == pytest.approx(1 / 3, abs=0.01)
+        assert r["cv_conf"] == pytest.approx(400.0, rel=0.05)

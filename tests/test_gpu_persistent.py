@@ -402,3 +402,35 @@ def test_sync_results_independent_of_timing(relib, precision, team, thermostat):
     assert np.allclose(a[3], b[3], rtol=1e-13, atol=0)
     with pytest.raises(Exception):
         relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 5, debug_delay_us=-1)
+
+
+def test_team_rebalancing(relib):
+    """Automatic teams are re-planned from the measured list-update rates
+    once every replica has done 500 steps: on a hot/cold ladder the hot
+    replicas (more frequent list updates) get more workgroups, every team
+    stays within one XCD's 32 workgroups, and the run is bitwise the same as
+    with teams proportional to N."""
+    R, N = 32, 3000  # (teams of at most 12 workgroups; 8 each to start with)
+    T = W.ladder(0.6, 3.0, R)
+    out = {}
+    for bal in (True, False):
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, 25, 6, team_balance=bal, watchdog_seconds=10)
+        t0 = e.query_teams()
+        assert np.all(t0 == t0[0])  # equal replicas: equal teams to start with
+        e.step(500)
+        e.step(60)  # (re-planned at the start of this call)
+        t1 = e.query_teams()
+        if bal:
+            assert t1.sum() <= 256 and t1.min() >= 1
+            _, reb = e.query_steps()
+            hot, cold = int(np.argmax(reb)), int(np.argmin(reb))
+            assert t1[hot] > t1[cold], (t1, reb)
+        else:
+            assert np.array_equal(t1, t0)
+        out[bal] = [e.get_state(r) for r in range(R)] + [e.query_energies(), e.query_slots()]
+        e.close()
+    for a, b in zip(out[True], out[False]):
+        if isinstance(a, tuple):
+            assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+        else:
+            assert np.array_equal(a, b)
