@@ -975,68 +975,110 @@ __device__ __forceinline__ void force_atom(const DevState& d, const StepArgs& sa
     force_epilogue<P, MODE>(d, sa, rd, r, ia, cur, step_next, par, pi, fx, fy, fz, e);
 }
 
-// Potential energy of replica r in FP64 with the whole workgroup: fixed-
-// order strided sums of the per-atom energies, then a fixed tree;
-// U = (1/2) sum_i e_i.  part: blockDim doubles of LDS.
 // Replica reductions sum over kRedWidth fixed slices (atom slots i = q mod
 // kRedWidth, in slot order) and then a fixed pairwise tree, so the result
 // does not depend on the workgroup size (the lockstep and the persistent
 // engine give the same bits).
 constexpr int kRedWidth = 256;
+// LDS doubles a replica reduction needs: two arrays of kRedWidth partial
+// sums and two values of the velocity rescale
+constexpr int kRedLds = 2 * kRedWidth + 2;
+
+// Slice sums of f(i) (one or two components) over the atom slots of replica
+// rd: slice q = sum over i = q, q + kRedWidth, ... < N in slot order, with
+// every thread's loads of up to 16 slots of a slice issued before its first
+// addition.  Slice q goes to a[q] (and b[q]).  Workgroup barrier at the end.
+template <int C, class F>
+__device__ __forceinline__ void slice_sums(int N, F f, double* a, double* b)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int q = tid; q < kRedWidth; q += nt) {
+        double s0 = 0.0, s1 = 0.0;
+        int i = q;
+        for (; i < N; i += 16 * kRedWidth) {
+            double2 t[16];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) t[k] = i + k * kRedWidth < N ? f(i + k * kRedWidth) : make_double2(0.0, 0.0);
+#pragma unroll
+            for (int k = 0; k < 16; ++k) {
+                if (i + k * kRedWidth < N) {  // (the same additions in the same order)
+                    s0 += t[k].x;
+                    if constexpr (C == 2) s1 += t[k].y;
+                }
+            }
+        }
+        a[q] = s0;
+        if constexpr (C == 2) b[q] = s1;
+    }
+    __syncthreads();
+}
+
+// The fixed pairwise tree over kRedWidth slice sums: a[q] += a[q + off] for
+// off = kRedWidth/2, ..., 1.  The levels down to 64 go through LDS with a
+// workgroup barrier each; the last six run in the first wave with shuffles,
+// which pair the same elements in the same order.  The total is returned to
+// thread 0 (other threads: unspecified).
+template <int C>
+__device__ __forceinline__ void tree_sums(double* a, double* b, double& ta, double& tb)
+{
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int off = kRedWidth >> 1; off >= 64; off >>= 1) {
+        for (int q = tid; q < off; q += nt) {
+            a[q] += a[q + off];
+            if constexpr (C == 2) b[q] += b[q + off];
+        }
+        __syncthreads();
+    }
+    ta = 0.0;
+    tb = 0.0;
+    if (tid < 64) {
+        double va = a[tid], vb = 0.0;
+        if constexpr (C == 2) vb = b[tid];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ua = __shfl_down(va, off, 64);
+            va = tid < off ? va + ua : va;
+            if constexpr (C == 2) {
+                const double ub = __shfl_down(vb, off, 64);
+                vb = tid < off ? vb + ub : vb;
+            }
+        }
+        ta = va;
+        tb = vb;
+    }
+}
 
 // Stochastic velocity rescale of replica r at step boundary s (Example
 // section: the thermostat; Bussi, Donadio and Parrinello 2007), computed by
-// one workgroup (part: 2 kRedWidth doubles) after a stopping force phase has
+// one workgroup (part: kRedLds doubles) after a stopping force phase has
 // left each atom's terms in svrq: K = sum v.v / 2 and the chi-square sum S of
 // N_f - 1 = 3N - 4 squared normals, both in FP64 (fixed slice order); R1 is
 // the first normal of atom 0 (Philox counter (0, s, r, purpose 4)); then
 //   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
 // Kbar = N_f T / 2 at the replica's temperature.  Returns the velocity
 // factor sqrt(K'/K) (1 when K = 0) to every thread; the fixed order gives
-// every workgroup that computes it the same bits.  Ends with a workgroup
+// every workgroup that computes it the same bits.  The last thread draws R1
+// and reads the temperature while the others load.  Ends with a workgroup
 // barrier.
 template <class P>
 __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
                              double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
-    const double2* q2 = d.svrq + rd.base;
-    for (int q = tid; q < kRedWidth; q += nt) {
-        double k2 = 0.0, chi = 0.0;
-        int i = q;
-        // (the same additions in the same order, eight loads in flight)
-        for (; i + 7 * kRedWidth < rd.N; i += 8 * kRedWidth) {
-            double2 t[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) t[k] = q2[i + k * kRedWidth];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) {
-                k2 += t[k].x;
-                chi += t[k].y;
-            }
-        }
-        for (; i < rd.N; i += kRedWidth) {
-            const double2 t = q2[i];
-            k2 += t.x;
-            chi += t.y;
-        }
-        part[q] = k2;
-        part[kRedWidth + q] = chi;
-    }
-    __syncthreads();
-    for (int off = kRedWidth >> 1; off > 0; off >>= 1) {
-        for (int q = tid; q < off; q += nt) {
-            part[q] += part[q + off];
-            part[kRedWidth + q] += part[kRedWidth + q + off];
-        }
-        __syncthreads();
-    }
-    if (tid == 0) {
-        const double K = 0.5 * part[0], S = part[kRedWidth];
+    const double Nf = 3.0 * rd.N - 3.0;
+    if (tid == nt - 1) {
         double R1, z1, z2;
         normals3d(draw(seed, 0u, (uint32_t)s, (uint32_t)r, kPurposeSVR), R1, z1, z2);
-        const double Nf = 3.0 * rd.N - 3.0;
-        const double Kbar = 0.5 * Nf * d.Tl[d.slot[r]];
+        part[2 * kRedWidth] = R1;
+        part[2 * kRedWidth + 1] = 0.5 * Nf * d.Tl[d.slot[r]];
+    }
+    const double2* q2 = d.svrq + rd.base;
+    slice_sums<2>(rd.N, [&](int i) { return q2[i]; }, part, part + kRedWidth);
+    double k2, chi;
+    tree_sums<2>(part, part + kRedWidth, k2, chi);
+    if (tid == 0) {
+        const double K = 0.5 * k2, S = chi;
+        const double R1 = part[2 * kRedWidth], Kbar = part[2 * kRedWidth + 1];
         double f = 1.0;
         if (K > 0.0) {
             const double Kn = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
@@ -1061,31 +1103,17 @@ __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t 
     __syncthreads();
 }
 
+// Potential energy of replica r in FP64 with the whole workgroup (part:
+// kRedLds doubles): U = (1/2) sum_i e_i over the per-atom energies, in the
+// fixed slice and tree order.
 template <class P>
 __device__ void energy_replica(const DevState& d, const RepDev& rd, int r, double* part)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
     const typename P::real* e = P::epot(d) + rd.base;
-    for (int q = tid; q < kRedWidth; q += nt) {
-        double s = 0.0;
-        int i = q;
-        // (the same additions in the same order, eight loads in flight)
-        for (; i + 7 * kRedWidth < rd.N; i += 8 * kRedWidth) {
-            typename P::real v[8];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v[k] = e[i + k * kRedWidth];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) s += (double)v[k];
-        }
-        for (; i < rd.N; i += kRedWidth) s += (double)e[i];
-        part[q] = s;
-    }
-    __syncthreads();
-    for (int off = kRedWidth >> 1; off > 0; off >>= 1) {
-        for (int q = tid; q < off; q += nt) part[q] += part[q + off];
-        __syncthreads();
-    }
-    if (tid == 0) d.U[r] = 0.5 * part[0];
+    slice_sums<1>(rd.N, [&](int i) { return make_double2((double)e[i], 0.0); }, part, nullptr);
+    double u, unused;
+    tree_sums<1>(part, nullptr, u, unused);
+    if (threadIdx.x == 0) d.U[r] = 0.5 * u;
     __syncthreads();
 }
 

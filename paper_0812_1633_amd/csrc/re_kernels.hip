@@ -372,7 +372,7 @@ __global__ __launch_bounds__(256) void k_force(DevState d, StepArgs sa)
 template <class P>
 __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
 {
-    __shared__ double part[512];
+    __shared__ double part[kRedLds];
     const int r = sa.r0 + blockIdx.x;
     const RepDev rd = d.rep[r];
     if (sa.do_u) energy_replica<P>(d, rd, r, part);

@@ -326,7 +326,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     constexpr int kStageK = (int)(64 / sizeof(typename P::pos_t));
     static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
-    __shared__ double dpart[2 * kRedWidth];
+    __shared__ double dpart[kRedLds];
     __shared__ int sh[4];
     __shared__ int lr_next;  // list build: next batch of atoms to hand out
     if (threadIdx.x == 0) lr_next = 0;
