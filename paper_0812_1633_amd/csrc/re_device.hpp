@@ -986,8 +986,10 @@ constexpr int kRedLds = 2 * kRedWidth + 2;
 
 // Slice sums of f(i) (one or two components) over the atom slots of replica
 // rd: slice q = sum over i = q, q + kRedWidth, ... < N in slot order, with
-// every thread's loads of up to 16 slots of a slice issued before its first
-// addition.  Slice q goes to a[q] (and b[q]).  Workgroup barrier at the end.
+// every thread's loads issued eight at a time, each round before its
+// additions (sixteen in flight cost the persistent kernel's step loop
+// register spills).  Slice q goes to a[q] (and b[q]).  Workgroup barrier at
+// the end.
 template <int C, class F>
 __device__ __forceinline__ void slice_sums(int N, F f, double* a, double* b)
 {
@@ -995,12 +997,12 @@ __device__ __forceinline__ void slice_sums(int N, F f, double* a, double* b)
     for (int q = tid; q < kRedWidth; q += nt) {
         double s0 = 0.0, s1 = 0.0;
         int i = q;
-        for (; i < N; i += 16 * kRedWidth) {
-            double2 t[16];
+        for (; i < N; i += 8 * kRedWidth) {
+            double2 t[8];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) t[k] = i + k * kRedWidth < N ? f(i + k * kRedWidth) : make_double2(0.0, 0.0);
+            for (int k = 0; k < 8; ++k) t[k] = i + k * kRedWidth < N ? f(i + k * kRedWidth) : make_double2(0.0, 0.0);
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
+            for (int k = 0; k < 8; ++k) {
                 if (i + k * kRedWidth < N) {  // (the same additions in the same order)
                     s0 += t[k].x;
                     if constexpr (C == 2) s1 += t[k].y;
@@ -1014,26 +1016,21 @@ __device__ __forceinline__ void slice_sums(int N, F f, double* a, double* b)
 }
 
 // The fixed pairwise tree over kRedWidth slice sums: a[q] += a[q + off] for
-// off = kRedWidth/2, ..., 1.  The levels down to 64 go through LDS with a
-// workgroup barrier each; the last six run in the first wave with shuffles,
-// which pair the same elements in the same order.  The total is returned to
-// thread 0 (other threads: unspecified).
+// off = kRedWidth/2, ..., 1, all in the first wave (its lane l holds slices
+// l, l + 64, l + 128, l + 192, which makes the first two levels additions in
+// registers; the last six are shuffles), pairing the same elements in the
+// same order.  The total is returned to thread 0 (other threads:
+// unspecified).  Needs the slice sums' workgroup barrier before it.
 template <int C>
-__device__ __forceinline__ void tree_sums(double* a, double* b, double& ta, double& tb)
+__device__ __forceinline__ void tree_sums(const double* a, const double* b, double& ta, double& tb)
 {
-    const int tid = threadIdx.x, nt = blockDim.x;
-    for (int off = kRedWidth >> 1; off >= 64; off >>= 1) {
-        for (int q = tid; q < off; q += nt) {
-            a[q] += a[q + off];
-            if constexpr (C == 2) b[q] += b[q + off];
-        }
-        __syncthreads();
-    }
+    static_assert(kRedWidth == 256, "the tree assumes four slices per lane");
+    const int tid = threadIdx.x;
     ta = 0.0;
     tb = 0.0;
     if (tid < 64) {
-        double va = a[tid], vb = 0.0;
-        if constexpr (C == 2) vb = b[tid];
+        double va = (a[tid] + a[tid + 128]) + (a[tid + 64] + a[tid + 192]), vb = 0.0;
+        if constexpr (C == 2) vb = (b[tid] + b[tid + 128]) + (b[tid + 64] + b[tid + 192]);
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
             const double ua = __shfl_down(va, off, 64);
@@ -1048,6 +1045,15 @@ __device__ __forceinline__ void tree_sums(double* a, double* b, double& ta, doub
     }
 }
 
+// R1 of the velocity rescale of replica r at step boundary s: the first
+// normal of atom 0's draw (Philox counter (0, s, r, purpose 4)).
+__device__ __forceinline__ double svr_normal(uint64_t seed, int64_t s, int r)
+{
+    double z0, z1, z2;
+    normals3d(draw(seed, 0u, (uint32_t)s, (uint32_t)r, kPurposeSVR), z0, z1, z2);
+    return z0;
+}
+
 // Stochastic velocity rescale of replica r at step boundary s (Example
 // section: the thermostat; Bussi, Donadio and Parrinello 2007), computed by
 // one workgroup (part: kRedLds doubles) after a stopping force phase has
@@ -1057,20 +1063,19 @@ __device__ __forceinline__ void tree_sums(double* a, double* b, double& ta, doub
 //   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
 // Kbar = N_f T / 2 at the replica's temperature.  Returns the velocity
 // factor sqrt(K'/K) (1 when K = 0) to every thread; the fixed order gives
-// every workgroup that computes it the same bits.  The last thread draws R1
-// and reads the temperature while the others load.  Ends with a workgroup
-// barrier.
+// every workgroup that computes it the same bits.  With `known` thread 0
+// holds the replica's temperature T and R1; without, the last thread draws
+// R1 and reads the temperature while the others load.  Ends with a
+// workgroup barrier.
 template <class P>
 __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
-                             double* part)
+                             bool known, double T, double R1, double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const double Nf = 3.0 * rd.N - 3.0;
-    if (tid == nt - 1) {
-        double R1, z1, z2;
-        normals3d(draw(seed, 0u, (uint32_t)s, (uint32_t)r, kPurposeSVR), R1, z1, z2);
-        part[2 * kRedWidth] = R1;
-        part[2 * kRedWidth + 1] = 0.5 * Nf * d.Tl[d.slot[r]];
+    if (!known && tid == nt - 1) {
+        part[2 * kRedWidth] = svr_normal(seed, s, r);
+        part[2 * kRedWidth + 1] = d.Tl[d.slot[r]];
     }
     const double2* q2 = d.svrq + rd.base;
     slice_sums<2>(rd.N, [&](int i) { return q2[i]; }, part, part + kRedWidth);
@@ -1078,7 +1083,11 @@ __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t
     tree_sums<2>(part, part + kRedWidth, k2, chi);
     if (tid == 0) {
         const double K = 0.5 * k2, S = chi;
-        const double R1 = part[2 * kRedWidth], Kbar = part[2 * kRedWidth + 1];
+        if (!known) {
+            R1 = part[2 * kRedWidth];
+            T = part[2 * kRedWidth + 1];
+        }
+        const double Kbar = 0.5 * Nf * T;
         double f = 1.0;
         if (K > 0.0) {
             const double Kn = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
@@ -1096,9 +1105,9 @@ __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t
 // velocity factor (alpha *= sqrt(K'/K)), by one workgroup.
 template <class P>
 __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
-                            double* part)
+                            bool known, double T, double R1, double* part)
 {
-    const double f = svr_factor<P>(d, rd, r, s, seed, c, part);
+    const double f = svr_factor<P>(d, rd, r, s, seed, c, known, T, R1, part);
     if (threadIdx.x == 0) d.alpha[r] *= f;
     __syncthreads();
 }

@@ -327,9 +327,15 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     static_assert(kTabWords <= kMaxCells + 1 && kMaxCells + 1 <= kPersistLdsWords, "LDS array too small");
     __shared__ int part[1024];
     __shared__ double dpart[kRedLds];
+    __shared__ double r1tab[64];
+    __shared__ long long r1lo;  // first boundary of r1tab (-1: none)
+    __shared__ double Tcur;     // the temperature the replica holds (thread 0's)
     __shared__ int sh[4];
     __shared__ int lr_next;  // list build: next batch of atoms to hand out
-    if (threadIdx.x == 0) lr_next = 0;
+    if (threadIdx.x == 0) {
+        lr_next = 0;
+        r1lo = -1;
+    }
     const PersistState& ps = pa.st;
     const CallParams& cp = *pa.call;
     const int b = blockIdx.x;
@@ -369,6 +375,20 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
     double Ucur = d.U[r];
+    // R1 of the velocity rescale at boundary sn, from a table of the 64
+    // boundaries from r1lo on that the first wave fills (a normal per lane)
+    // when sn is not in it; called by the whole workgroup
+    auto svr_r1 = [&](int64_t sn) -> double {
+        const long long lo = r1lo;
+        if (lo < 0 || sn < lo || sn >= lo + 64) {
+            if (tid < 64) r1tab[tid] = svr_normal(pa.sa.seed, sn + tid, r);
+            __syncthreads();
+            if (tid == 0) r1lo = sn;
+            __syncthreads();
+            return r1tab[0];
+        }
+        return r1tab[sn - lo];
+    };
     // synchronous form: the next multiple of N_x not below the boundaries
     // planned so far (advanced as they pass; no 64-bit division per step)
     int64_t xnext = (s + pa.Nx - 1) / pa.Nx * pa.Nx;
@@ -498,6 +518,9 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         }
         maybe_pause(pa, b, s, 0);
         ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        // the temperature held until the next stopped boundary (only its
+        // join changes the replica's slot), for the velocity rescale
+        if (pa.sa.thermo == kThermoSVR && tid == 0) Tcur = d.Tl[d.slot[r]];
         PT_MARK(0);
         if (ctl & kCtlExit) break;
         // ---- first half of step s -> s+1
@@ -690,7 +713,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 // member computes the factor (the same bits in each), then the
                 // first half of the next step for its own atoms with the
                 // pending factor (1 between exchanges) times it applied
-                const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, dpart);
+                const double R1 = svr_r1(s);
+                const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
                 const double a64 = d.alpha[r] * fct;
                 for (int i = i0 + tid; i < i1; i += nt) start_atom_scaled<P>(d, pa.sa, rd, r, i, cur, s, a64);
                 if (leader && tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = plan(s + 1);
@@ -712,7 +736,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                         Ucur = d.U[r];
                     }
                     if (pa.sa.thermo == kThermoSVR) {
-                        svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, dpart);
+                        const double R1 = svr_r1(s);
+                        svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
                         if (tid == 0) ps.apend[r] = 1;
                     }
                 }
