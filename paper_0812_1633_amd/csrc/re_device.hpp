@@ -1107,16 +1107,18 @@ template <class P>
 __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
                             bool known, double T, double R1, double* part)
 {
+    const double a = d.alpha[r];  // (loaded before the reduction's barriers)
     const double f = svr_factor<P>(d, rd, r, s, seed, c, known, T, R1, part);
-    if (threadIdx.x == 0) d.alpha[r] *= f;
+    if (threadIdx.x == 0) d.alpha[r] = a * f;
     __syncthreads();
 }
 
 // Potential energy of replica r in FP64 with the whole workgroup (part:
 // kRedLds doubles): U = (1/2) sum_i e_i over the per-atom energies, in the
-// fixed slice and tree order.
+// fixed slice and tree order, stored to d.U[r] and returned to thread 0
+// (other threads: unspecified).
 template <class P>
-__device__ void energy_replica(const DevState& d, const RepDev& rd, int r, double* part)
+__device__ double energy_replica(const DevState& d, const RepDev& rd, int r, double* part)
 {
     const typename P::real* e = P::epot(d) + rd.base;
     slice_sums<1>(rd.N, [&](int i) { return make_double2((double)e[i], 0.0); }, part, nullptr);
@@ -1124,6 +1126,7 @@ __device__ void energy_replica(const DevState& d, const RepDev& rd, int r, doubl
     tree_sums<1>(part, nullptr, u, unused);
     if (threadIdx.x == 0) d.U[r] = 0.5 * u;
     __syncthreads();
+    return 0.5 * u;
 }
 
 }  // namespace re

@@ -48,7 +48,8 @@ __device__ __forceinline__ uint64_t clock100()
 // own row; re_debug_phase_ticks copies the rows out and clears them.
 #ifdef RE_PHASE_TIMERS
 // phases 0..7 of the step loop; 8, 9: inside the exchange join, the wait
-// at the gate and the wait for the partner's post
+// at the gate and the wait for the partner's post; 10, 11: the leader's
+// potential energy and velocity rescale at a stopped boundary
 constexpr int kPhases = 12;
 __device__ unsigned long long g_phase_ticks[1024 * kPhases];
 #define PT_INIT() uint64_t pt_last = clock100()
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     bool join_pending = false;
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
-    double Ucur = d.U[r];
+    double Ucur = d.U[r];  // potential energy at the last stop (thread 0's is used)
     // R1 of the velocity rescale at boundary sn, from a table of the 64
     // boundaries from r1lo on that the first wave fills (a normal per lane)
     // when sn is not in it; called by the whole workgroup
@@ -713,9 +714,10 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 // member computes the factor (the same bits in each), then the
                 // first half of the next step for its own atoms with the
                 // pending factor (1 between exchanges) times it applied
+                const double apend = d.alpha[r];  // (loaded before the reduction's barriers)
                 const double R1 = svr_r1(s);
                 const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
-                const double a64 = d.alpha[r] * fct;
+                const double a64 = apend * fct;
                 for (int i = i0 + tid; i < i1; i += nt) start_atom_scaled<P>(d, pa.sa, rd, r, i, cur, s, a64);
                 if (leader && tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = plan(s + 1);
                 if (!team_sync(pa, ctr, epoch, t, one_xcd, &sh[3])) {
@@ -731,15 +733,14 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             }
             if (stop) {
                 if (leader) {
-                    if (with_u) {
-                        energy_replica<P>(d, rd, r, dpart);
-                        Ucur = d.U[r];
-                    }
+                    if (with_u) Ucur = energy_replica<P>(d, rd, r, dpart);
+                    PT_MARK(10);
                     if (pa.sa.thermo == kThermoSVR) {
                         const double R1 = svr_r1(s);
                         svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
                         if (tid == 0) ps.apend[r] = 1;
                     }
+                    PT_MARK(11);
                 }
                 PT_MARK(6);
                 join_pending = (ctl & kCtlJoin) != 0;
