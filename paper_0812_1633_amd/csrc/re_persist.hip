@@ -194,9 +194,10 @@ __device__ __forceinline__ void maybe_pause(const PersistArgs& pa, int b, int64_
 }
 
 // The exchange join of replica r at its boundary s (energy U) for attempt k,
-// run by the whole leader workgroup.  Returns false on abort.
+// run by the whole leader workgroup.  Thread 0 keeps *T, the temperature the
+// replica holds, up to date.  Returns false on abort.
 __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const CallParams& cp, int r, int64_t k,
-                              int64_t s, double U, int* sh)
+                              int64_t s, double U, int* sh, double* T)
 {
     const PersistState& ps = pa.st;
     const int R = pa.sa.R;
@@ -243,6 +244,13 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
         __hip_atomic_store(ps.post + r, k + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         int newslot = jme;
         if (q >= 0) {
+            // what does not depend on the partner's post is read or drawn
+            // before the wait for it
+            const int jlo = jme < jp ? jme : jp, jhi = jme < jp ? jp : jme;
+            const int a = jme < jp ? r : q, b = jme < jp ? q : r;
+            const double Ta = d.Tl[jlo], Tb = d.Tl[jhi];
+            const double u = uniform53(pa.sa.seed, k, a < b ? a : b);
+            const double apend = d.alpha[r];
 #ifdef RE_PHASE_TIMERS
             const uint64_t tp0 = clock100();
 #endif
@@ -253,12 +261,8 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
             if (ok) {
                 const double Uq = ps.upost[(size_t)p * R + q];
                 const int64_t sq = ps.spost[(size_t)p * R + q];
-                const int jlo = jme < jp ? jme : jp, jhi = jme < jp ? jp : jme;
-                const int a = jme < jp ? r : q, b = jme < jp ? q : r;
                 const double Ua = jme < jp ? U : Uq, Ub = jme < jp ? Uq : U;
-                const double Ta = d.Tl[jlo], Tb = d.Tl[jhi];
                 const double delta = (1.0 / Ta - 1.0 / Tb) * (Ua - Ub);
-                const double u = uniform53(pa.sa.seed, k, a < b ? a : b);
                 const int acc = (delta >= 0.0 || u < exp(delta)) ? 1 : 0;
                 if (jme == jlo) {
                     atomicAdd((unsigned long long*)&d.attempts[jlo], 1ull);
@@ -283,9 +287,11 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
                 }
                 if (acc) {
                     newslot = jp;
-                    d.alpha[r] *= sqrt(d.Tl[jp] / d.Tl[jme]);
-                    d.c2[r] = sqrt((1.0 - pa.c1sq) * d.Tl[jp]);
+                    const double Tme = jme == jlo ? Ta : Tb, Tp = jme == jlo ? Tb : Ta;
+                    d.alpha[r] = apend * sqrt(Tp / Tme);
+                    d.c2[r] = sqrt((1.0 - pa.c1sq) * Tp);
                     ps.apend[r] = 1;
+                    *T = Tp;
                 }
             }
         }
@@ -330,7 +336,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     __shared__ double dpart[kRedLds];
     __shared__ double r1tab[64];
     __shared__ long long r1lo;  // first boundary of r1tab (-1: none)
-    __shared__ double Tcur;     // the temperature the replica holds (thread 0's)
+    __shared__ double Tcur;     // the temperature the replica holds (thread 0's view)
     __shared__ int sh[4];
     __shared__ int lr_next;  // list build: next batch of atoms to hand out
     if (threadIdx.x == 0) {
@@ -376,6 +382,8 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
     double Ucur = d.U[r];  // potential energy at the last stop (thread 0's is used)
+    // the temperature the replica holds (in thread 0), kept by its joins
+    if (tid == 0) Tcur = d.Tl[d.slot[r]];
     // R1 of the velocity rescale at boundary sn, from a table of the 64
     // boundaries from r1lo on that the first wave fills (a normal per lane)
     // when sn is not in it; called by the whole workgroup
@@ -438,7 +446,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         // ---- at a stopped boundary s
         if (leader) {
             if (join_pending) {
-                ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
+                ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh, &Tcur);
                 knext += 1;
                 jprev = s;
                 if (cp.mode == kModeSchedule) asched += 1;
@@ -494,7 +502,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                         const int act = sh[2];
                         __syncthreads();
                         if (act == 1) {
-                            ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
+                            ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh, &Tcur);
                             knext += 1;
                             jprev = s;
                         } else if (act == 2) {
@@ -519,9 +527,6 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         }
         maybe_pause(pa, b, s, 0);
         ctl = __hip_atomic_load(ps.ctl + (size_t)((s + 1) & 1) * R + r, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        // the temperature held until the next stopped boundary (only its
-        // join changes the replica's slot), for the velocity rescale
-        if (pa.sa.thermo == kThermoSVR && tid == 0) Tcur = d.Tl[d.slot[r]];
         PT_MARK(0);
         if (ctl & kCtlExit) break;
         // ---- first half of step s -> s+1
