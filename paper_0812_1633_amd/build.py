@@ -65,4 +65,12 @@ def build(verbose: bool = False, defines=(), lib_path: str = LIB) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    import argparse
+    ap = argparse.ArgumentParser(description="build libre_hip.so for gfx950")
+    ap.add_argument("--phase-timers", action="store_true",
+                    help="build libre_hip_timers.so instead, with the persistent kernel's phase timers")
+    a = ap.parse_args()
+    if a.phase_timers:
+        print(build(verbose=True, defines=("RE_PHASE_TIMERS",), lib_path=os.path.join(HERE, "libre_hip_timers.so")))
+    else:
+        print(build(verbose=True))

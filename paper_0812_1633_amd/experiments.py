@@ -21,8 +21,9 @@ the skin, time step 0.005, stochastic velocity rescaling, and temperatures
 T_k = 0.7 * 1.0275^k.  <N_x> is the average number of steps a replica does
 between two attempts (total steps of all replicas / (replicas x attempts)).
 
-Command line: ``python -m paper_0812_1633_amd.experiments efficiency|diffusion
-[--out FILE] [...]`` prints (and writes) one JSON document.
+Command line: ``python -m paper_0812_1633_amd.experiments
+efficiency|diffusion|acceptance|phases [--out FILE] [...]`` prints (and
+writes) one JSON document.
 """
 from __future__ import annotations
 
@@ -301,11 +302,13 @@ def phases(lib_path, Nr=16, modes=(("async", None), ("async", 1), ("sync", 5)), 
            N=PAPER["N"], seed=1, workload=None, threads_per_atom=2):
     """Microseconds per step (and per workgroup) in each phase of the
     persistent kernel, from a library built with RE_PHASE_TIMERS
-    (``paper_0812_1633_amd.build.build(defines=("RE_PHASE_TIMERS",),
-    lib_path=...)``): on the paper's workload at N_r replicas without
-    exchanges and with the given (mode, N_x); or, with ``workload``, on that
-    benchmark workload (its own exchange settings, melted start).  The last
-    two phases lie inside the first."""
+    (``python -m paper_0812_1633_amd.build --phase-timers`` writes
+    ``libre_hip_timers.so``): on the paper's workload at N_r replicas
+    without exchanges and with the given (mode, N_x); or, with ``workload``,
+    on that benchmark workload (its own exchange settings, melted start).
+    The two join waits lie inside the first phase.  With exchanges, also the
+    microseconds per attempt of the team leaders (the workgroups that time
+    the stop reductions) and of the other members."""
     import ctypes as C
     from . import re as R
     R.LIB_PATH = lib_path
@@ -338,9 +341,16 @@ def phases(lib_path, Nr=16, modes=(("async", None), ("async", 1), ("sync", 5)), 
         act = t[:, :8].sum(1) > 0
         done = float((s1 - s0).sum())
         us = t[act].mean(0)[:len(PHASES)] / 100.0 / (done / Nr)  # 100 MHz ticks
-        rows.append(dict(mode=mode, Nx=nx, steps_per_s_per_replica=done / Nr / (t1 - t0),
-                         mean_Nx=(done / (Nr * (a1 - a0))) if a1 > a0 else None,
-                         us_per_step=dict(zip(PHASES, [float(x) for x in us]))))
+        row = dict(mode=mode, Nx=nx, steps_per_s_per_replica=done / Nr / (t1 - t0),
+                   mean_Nx=(done / (Nr * (a1 - a0))) if a1 > a0 else None,
+                   us_per_step=dict(zip(PHASES, [float(x) for x in us])))
+        lead = act & (t[:, 10] + t[:, 11] > 0)
+        if a1 > a0 and lead.any() and (act & ~lead).any():
+            # every replica joins every attempt (asynchronous and synchronous forms)
+            per = lambda m: dict(zip(PHASES, [float(x) for x in t[m].mean(0)[:len(PHASES)] / 100.0 / (a1 - a0)]))
+            row["us_per_attempt_leader"] = per(lead)
+            row["us_per_attempt_member"] = per(act & ~lead)
+        rows.append(row)
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     return dict(experiment="phases", workload=workload or dict(PAPER, N=N), Nr=Nr, steps=steps, warmup=warmup,
                 rows=rows)
