@@ -1063,18 +1063,18 @@ __device__ __forceinline__ double svr_normal(uint64_t seed, int64_t s, int r)
 //   K' = K + (1 - c)(Kbar (R1^2 + S) / N_f - K) + 2 R1 sqrt(c (1 - c) K Kbar / N_f),
 // Kbar = N_f T / 2 at the replica's temperature.  Returns the velocity
 // factor sqrt(K'/K) (1 when K = 0) to every thread; the fixed order gives
-// every workgroup that computes it the same bits.  With `known` thread 0
-// holds the replica's temperature T and R1; without, the last thread draws
-// R1 and reads the temperature while the others load.  Ends with a
+// every workgroup that computes it the same bits.  R1 is given to thread 0
+// (r1_known) or drawn here; the last thread draws it and reads the
+// temperature the replica holds while the others load.  Ends with a
 // workgroup barrier.
 template <class P>
 __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
-                             bool known, double T, double R1, double* part)
+                             bool r1_known, double R1, double* part)
 {
     const int tid = threadIdx.x, nt = blockDim.x;
     const double Nf = 3.0 * rd.N - 3.0;
-    if (!known && tid == nt - 1) {
-        part[2 * kRedWidth] = svr_normal(seed, s, r);
+    if (tid == nt - 1) {
+        if (!r1_known) part[2 * kRedWidth] = svr_normal(seed, s, r);
         part[2 * kRedWidth + 1] = d.Tl[d.slot[r]];
     }
     const double2* q2 = d.svrq + rd.base;
@@ -1083,11 +1083,8 @@ __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t
     tree_sums<2>(part, part + kRedWidth, k2, chi);
     if (tid == 0) {
         const double K = 0.5 * k2, S = chi;
-        if (!known) {
-            R1 = part[2 * kRedWidth];
-            T = part[2 * kRedWidth + 1];
-        }
-        const double Kbar = 0.5 * Nf * T;
+        if (!r1_known) R1 = part[2 * kRedWidth];
+        const double Kbar = 0.5 * Nf * part[2 * kRedWidth + 1];
         double f = 1.0;
         if (K > 0.0) {
             const double Kn = K + (1.0 - c) * (Kbar * (R1 * R1 + S) / Nf - K) + 2.0 * R1 * sqrt(c * (1.0 - c) * K * Kbar / Nf);
@@ -1105,10 +1102,10 @@ __device__ double svr_factor(const DevState& d, const RepDev& rd, int r, int64_t
 // velocity factor (alpha *= sqrt(K'/K)), by one workgroup.
 template <class P>
 __device__ void svr_replica(const DevState& d, const RepDev& rd, int r, int64_t s, uint64_t seed, double c,
-                            bool known, double T, double R1, double* part)
+                            bool r1_known, double R1, double* part)
 {
     const double a = d.alpha[r];  // (loaded before the reduction's barriers)
-    const double f = svr_factor<P>(d, rd, r, s, seed, c, known, T, R1, part);
+    const double f = svr_factor<P>(d, rd, r, s, seed, c, r1_known, R1, part);
     if (threadIdx.x == 0) d.alpha[r] = a * f;
     __syncthreads();
 }

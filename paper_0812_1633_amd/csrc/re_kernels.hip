@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_energy(DevState d, StepArgs sa)
     const int r = sa.r0 + blockIdx.x;
     const RepDev rd = d.rep[r];
     if (sa.do_u) energy_replica<P>(d, rd, r, part);
-    if (sa.do_svr) svr_replica<P>(d, rd, r, sa.step, sa.seed, sa.svr_c, false, 0.0, 0.0, part);
+    if (sa.do_svr) svr_replica<P>(d, rd, r, sa.step, sa.seed, sa.svr_c, false, 0.0, part);
 }
 
 // ---------------------------------------------------------------------------

@@ -194,10 +194,9 @@ __device__ __forceinline__ void maybe_pause(const PersistArgs& pa, int b, int64_
 }
 
 // The exchange join of replica r at its boundary s (energy U) for attempt k,
-// run by the whole leader workgroup.  Thread 0 keeps *T, the temperature the
-// replica holds, up to date.  Returns false on abort.
+// run by the whole leader workgroup.  Returns false on abort.
 __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const CallParams& cp, int r, int64_t k,
-                              int64_t s, double U, int* sh, double* T)
+                              int64_t s, double U, int* sh)
 {
     const PersistState& ps = pa.st;
     const int R = pa.sa.R;
@@ -291,7 +290,6 @@ __device__ bool exchange_join(const DevState& d, const PersistArgs& pa, const Ca
                     d.alpha[r] = apend * sqrt(Tp / Tme);
                     d.c2[r] = sqrt((1.0 - pa.c1sq) * Tp);
                     ps.apend[r] = 1;
-                    *T = Tp;
                 }
             }
         }
@@ -336,7 +334,6 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     __shared__ double dpart[kRedLds];
     __shared__ double r1tab[64];
     __shared__ long long r1lo;  // first boundary of r1tab (-1: none)
-    __shared__ double Tcur;     // the temperature the replica holds (thread 0's view)
     __shared__ int sh[4];
     __shared__ int lr_next;  // list build: next batch of atoms to hand out
     if (threadIdx.x == 0) {
@@ -382,8 +379,6 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
     bool parked = false;
     bool reached = false;  // asynchronous mode: this replica reached its target
     double Ucur = d.U[r];  // potential energy at the last stop (thread 0's is used)
-    // the temperature the replica holds (in thread 0), kept by its joins
-    if (tid == 0) Tcur = d.Tl[d.slot[r]];
     // R1 of the velocity rescale at boundary sn, from a table of the 64
     // boundaries from r1lo on that the first wave fills (a normal per lane)
     // when sn is not in it; called by the whole workgroup
@@ -446,7 +441,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
         // ---- at a stopped boundary s
         if (leader) {
             if (join_pending) {
-                ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh, &Tcur);
+                ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
                 knext += 1;
                 jprev = s;
                 if (cp.mode == kModeSchedule) asched += 1;
@@ -502,7 +497,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                         const int act = sh[2];
                         __syncthreads();
                         if (act == 1) {
-                            ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh, &Tcur);
+                            ok = exchange_join(d, pa, cp, r, knext, s, Ucur, sh);
                             knext += 1;
                             jprev = s;
                         } else if (act == 2) {
@@ -721,7 +716,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                 // pending factor (1 between exchanges) times it applied
                 const double apend = d.alpha[r];  // (loaded before the reduction's barriers)
                 const double R1 = svr_r1(s);
-                const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
+                const double fct = svr_factor<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, R1, dpart);
                 const double a64 = apend * fct;
                 for (int i = i0 + tid; i < i1; i += nt) start_atom_scaled<P>(d, pa.sa, rd, r, i, cur, s, a64);
                 if (leader && tid == 0) ps.ctl[(size_t)((s + 1) & 1) * R + r] = plan(s + 1);
@@ -742,7 +737,7 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                     PT_MARK(10);
                     if (pa.sa.thermo == kThermoSVR) {
                         const double R1 = svr_r1(s);
-                        svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, Tcur, R1, dpart);
+                        svr_replica<P>(d, rd, r, s, pa.sa.seed, pa.sa.svr_c, true, R1, dpart);
                         if (tid == 0) ps.apend[r] = 1;
                     }
                     PT_MARK(11);

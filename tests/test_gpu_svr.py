@@ -93,6 +93,31 @@ def test_svr_persistent_equals_lockstep(relib, precision):
     assert np.allclose(a[3], b[3], rtol=1e-13, atol=0)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_svr_accepted_swaps_inside_one_call(relib, precision):
+    """A narrow ladder (acceptance near 1) and teams of 4 workgroups: swaps
+    accepted inside one persistent call must change the temperature every
+    team member thermostats to, exactly as between lockstep launches."""
+    R, N, Nx = 4, 600, 5
+    T = W.ladder(1.0, 1.03, R)
+    out = {}
+    for eng in ("lockstep", "persistent"):
+        kw = dict(team_size=4) if eng == "persistent" else {}
+        e = relib.Engine([N] * R, T, 0.8442, RC, SKIN, DT, Nx, 8, precision=precision, engine=eng,
+                         thermostat="svr", svr_tau=0.1, watchdog_seconds=5, **kw)
+        e.step(120)
+        st = [e.get_state(r) for r in range(R)]
+        out[eng] = (st, e.query_slots(), e.query_acceptance(), e.query_energies())
+        e.close()
+    a, b = out["lockstep"], out["persistent"]
+    assert int(np.sum(a[2][1])) >= 5  # accepted swaps inside the call
+    for r in range(R):
+        assert np.array_equal(a[0][r][0], b[0][r][0]) and np.array_equal(a[0][r][1], b[0][r][1]), r
+    assert np.array_equal(a[1], b[1])
+    assert np.array_equal(a[2][0], b[2][0]) and np.array_equal(a[2][1], b[2][1])
+    assert np.allclose(a[3], b[3], rtol=1e-13, atol=0)
+
+
 def test_svr_sync_run_matches_oracle_fp64(relib):
     R, N, Nx, steps, seed = 4, 256, 20, 200, 9
     T = W.ladder(0.7, 1.2, R)
