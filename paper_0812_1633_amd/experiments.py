@@ -271,10 +271,11 @@ def acceptance(Nr=48, Nx=5, steps=20000, warmup=2000, N=PAPER["N"], seed=1):
 # ---------------------------------------------------------------------------
 # Where the persistent kernel's time goes (instrumented build)
 
-PHASES = ("boundary, exchange join, barrier", "first half of a step, barrier", "reorder, barrier", "list build",
-          "force pass (the workgroup's first wave)", "team barrier after the forces",
-          "energy / rescale reductions at a stop (leader)", "rest of the workgroup after the force pass",
-          "exchange join: wait at the gate", "exchange join: wait for the partner")
+PHASES = ("boundary, exchange join, barrier", "first half of a step (with the rescale), barrier", "reorder, barrier",
+          "list build", "force pass (the workgroup's first wave)", "team barrier after the forces",
+          "rest of a stop", "rest of the workgroup after the force pass",
+          "exchange join: wait at the gate", "exchange join: wait for the partner",
+          "stop: the leader's potential energy", "stop: the leader's velocity rescale")
 
 
 def _workload_engine(R, name, melt=500, equil=500, **kw):
