@@ -140,6 +140,9 @@ def main():
                     help="steps of the batched FP64 form (the precision effect alone; 0: skip)")
     ap.add_argument("--svr-steps", type=int, default=1000,
                     help="steps of the same workload under stochastic velocity rescaling (0: skip)")
+    ap.add_argument("--exchange", choices=["sync", "async"], default="sync",
+                    help="exchange timing of the measured form (async: persistent engine; every step of every "
+                         "replica counted, the call ending when all have done --steps)")
     ap.add_argument("--attempt-reps", type=int, default=10,
                     help="windows with and without an exchange attempt, for the per-attempt cost")
     ap.add_argument("--no-cpu", action="store_true")
@@ -182,7 +185,10 @@ def main():
 
     # ---- batched mixed-precision form ------------------------------------
     progress("%s: %d replicas, %d atoms; creating the context" % (args.workload, Rn, atoms))
-    eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune)
+    xkw = {"exchange": "async"} if args.exchange == "async" else {}
+    if xkw and tune.get("engine", "persistent") != "persistent":
+        raise SystemExit("bench.py: asynchronous exchanges run in the persistent engine")
+    eng = R.Engine(N, T, 0.0, rc, skin, dt, Nx, seed, precision="mixed", form="batched", **kw, **tune, **xkw)
     engine_used, tpa_used, team_used = eng.query_config()
     lanes = eng.query_lanes()
     lanes_used = (int(lanes[0]) if len(set(lanes.tolist())) == 1
@@ -204,7 +210,7 @@ def main():
     # the timed window holds an exchange attempt: its middle step is a
     # multiple of N_x (untimed padding steps before it)
     s_now = int(eng.query_steps()[0][0])
-    pad = (-(s_now + (args.steps + 1) // 2)) % Nx
+    pad = (-(s_now + (args.steps + 1) // 2)) % Nx if not xkw else 0
     eng.step(pad)
     steps0, reb0 = eng.query_steps()
     att0, acc0 = eng.query_acceptance()
@@ -220,7 +226,8 @@ def main():
     att1, acc1 = eng.query_acceptance()
     done = int(((steps1 - steps0) * N).sum())
     value = done / (t1 - t0)
-    ms_per_step = 1e3 * (t1 - t0) / args.steps
+    # (asynchronous: per mean step of a replica, as replicas do different counts)
+    ms_per_step = 1e3 * (t1 - t0) / (args.steps if not xkw else float((steps1 - steps0).mean()))
     win_att = int((att1 - att0).sum())
     win_acc = int((acc1 - acc0).sum())
     progress("%d timed steps: %.4f ms per step, %d exchange records in the window" % (args.steps, ms_per_step,
@@ -230,7 +237,7 @@ def main():
     # attempt (starting at a multiple of N_x) against the same windows with
     # one attempt in their middle (untimed steps realign between them)
     attempt = None
-    if args.attempt_reps > 0 and Nx >= 3:
+    if args.attempt_reps > 0 and Nx >= 3 and not xkw:
         tA, tB = [], []
         for rep in range(args.attempt_reps):
             for kind in ("A", "B"):
@@ -370,7 +377,7 @@ def main():
                       "atoms_per_replica": int(N[0]) if len(set(N.tolist())) == 1 else "uneven",
                       "rho": float(rho[0]) if len(set(rho.tolist())) == 1 else "uneven",
                       "T_ladder": [float(T[0]), float(T[-1])], "r_c": rc, "skin": skin, "dt": dt, "N_x": Nx,
-                      "start": start, "exchange": "synchronous",
+                      "start": start, "exchange": "asynchronous" if xkw else "synchronous",
                       "precision": "FP32 pair arithmetic, 32-bit fixed-point positions, FP64 energies/exchange",
                       "engine": engine_used, "threads_per_atom": tpa_used, "team_size": team_used,
                       "lanes_per_replica": lanes_used,
