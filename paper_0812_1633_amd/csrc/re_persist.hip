@@ -621,41 +621,52 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
             // with TPA > 1 the sums of a pass go through LDS so that the
             // epilogues run one atom per thread (in the lanes of the atom's
             // group all but one would idle); LDS free between list builds
-            auto force_pass = [&](auto mode, auto lanes, const typename P::pos_t* fpos, int a0, int a1)
-                                  __attribute__((always_inline)) {
+            // (the stash takes the sums of G passes, and the epilogues of a
+            // group run together: with the positions in LDS one pass per group,
+            // else TL passes, so that every thread of the workgroup has an
+            // epilogue atom instead of one in TL)
+            auto force_pass = [&](auto mode, auto lanes, auto group, const typename P::pos_t* fpos, int a0,
+                                  int a1) __attribute__((always_inline)) {
                 constexpr int M = decltype(mode)::value;
                 constexpr int TL = decltype(lanes)::value;
+                constexpr int G = decltype(group)::value;
                 using real = typename P::real;
                 using real4 = typename P::vel_t;
                 real4* lf = reinterpret_cast<real4*>(cnt + stash_at);
-                typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + apb);
-                for (int base = a0; base < a1; base += apb) {
-                    const int ia = base + tid / TL;
-                    typename P::pos_t pi;
-                    real fx, fy, fz, e;
-                    force_sum<P, M, TL>(d, pa.sa, rd, fpos, ia, tid % TL, ia < a1, pi, fx, fy, fz, e);
+                typename P::pos_t* lp = reinterpret_cast<typename P::pos_t*>(lf + G * apb);
+                for (int base = a0; base < a1; base += G * apb) {
                     if constexpr (TL == 1) {
+                        const int ia = base + tid;
+                        typename P::pos_t pi;
+                        real fx, fy, fz, e;
+                        force_sum<P, M, TL>(d, pa.sa, rd, fpos, ia, 0, ia < a1, pi, fx, fy, fz, e);
                         if (ia < a1) force_epilogue<P, M>(d, pa.sa, rd, r, ia, cur, s + 1, par, pi, fx, fy, fz, e);
                     } else {
+                        for (int g = 0; g < G; ++g) {
+                            const int ia = base + g * apb + tid / TL;
+                            typename P::pos_t pi;
+                            real fx, fy, fz, e;
+                            force_sum<P, M, TL>(d, pa.sa, rd, fpos, ia, tid % TL, ia < a1, pi, fx, fy, fz, e);
+                            if (tid % TL == 0 && ia < a1) {
+                                real4 f;
+                                f.x = fx;
+                                f.y = fy;
+                                f.z = fz;
+                                f.w = e;
+                                lf[g * apb + tid / TL] = f;
+                                lp[g * apb + tid / TL] = pi;
+                            }
+                        }
                         // the velocity and x_ref of this thread's epilogue atom
                         // are loaded before the barrier, so that their latency
                         // overlaps the wait for the other waves' sums
                         const int ja = base + tid;
-                        const bool epi = tid < apb && ja < a1;
+                        const bool epi = tid < G * apb && ja < a1;
                         real4 v0{};
                         typename P::pos_t xr0{};
                         if (epi) {
                             if constexpr (M != kQuery) v0 = P::vel(d)[rd.base + ja];
                             if constexpr (M == kFused) xr0 = P::xref(d)[rd.base + ja];
-                        }
-                        if (tid % TL == 0 && ia < a1) {
-                            real4 f;
-                            f.x = fx;
-                            f.y = fy;
-                            f.z = fz;
-                            f.w = e;
-                            lf[tid / TL] = f;
-                            lp[tid / TL] = pi;
                         }
                         __syncthreads();
                         if (epi) {
@@ -663,18 +674,18 @@ __global__ __launch_bounds__(1024) void k_persist(DevState d, PersistArgs pa)
                             force_epilogue_v<P, M>(d, pa.sa, rd, r, ja, cur, s + 1, par, lp[tid], f.x, f.y, f.z, f.w,
                                                    v0, xr0);
                         }
-                        if (base + apb < a1) __syncthreads();
+                        if (base + G * apb < a1) __syncthreads();
                     }
                 }
             };
-            static_assert(2 * 512 * sizeof(double4) <= sizeof(int) * kPersistLdsWords, "force stash exceeds LDS");
+            static_assert(2 * 1024 * sizeof(double4) <= sizeof(int) * kPersistLdsWords, "force stash exceeds LDS");
             // (separate calls for each position source, so that each inlined
             // copy knows its address space)
             auto run_lanes = [&](auto mode, auto lanes) __attribute__((always_inline)) {
                 if (lds_pos)
-                    force_pass(mode, lanes, lpos, i0, i1);
+                    force_pass(mode, lanes, std::integral_constant<int, 1>{}, lpos, i0, i1);
                 else
-                    force_pass(mode, lanes, gpos, i0, i1);
+                    force_pass(mode, lanes, lanes, gpos, i0, i1);
             };
             auto run = [&](auto mode) __attribute__((always_inline)) {
                 if constexpr (TPA != 0) {
