@@ -1020,7 +1020,8 @@ __device__ __forceinline__ void slice_sums(int N, F f, double* a, double* b)
 // l, l + 64, l + 128, l + 192, which makes the first two levels additions in
 // registers; the last six are shuffles), pairing the same elements in the
 // same order.  The total is returned to thread 0 (other threads:
-// unspecified).  Needs the slice sums' workgroup barrier before it.
+// unspecified).  Needs a workgroup of at least 64 threads and the slice
+// sums' workgroup barrier before it.
 template <int C>
 __device__ __forceinline__ void tree_sums(const double* a, const double* b, double& ta, double& tb)
 {
