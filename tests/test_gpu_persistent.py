@@ -348,21 +348,23 @@ def test_list_key_staging_paths_agree(relib, precision):
     assert np.array_equal(a[3], b[3])
 
 
-@pytest.mark.parametrize("tpa,nfit", [(2, 8192), (4, 8704)])
-def test_position_copy_at_its_limit(relib, tpa, nfit):
+@pytest.mark.parametrize("tpa,nfit,precision", [(1, 9216, "mixed"), (2, 8192, "mixed"), (4, 8704, "mixed"),
+                                                 (8, 8960, "mixed"), (2, 2432, "fp64"), (8, 2432, "fp64")])
+def test_position_copy_at_its_limit(relib, tpa, nfit, precision):
     """The mixed form's LDS copy of the positions (16 B per atom) and the
     stash of per-atom sums (32 B per atom of a pass: 1024 / tpa atoms) share
     the persistent workgroup's 144 KiB: replicas of nfit atoms fill it
-    exactly, one atom more reads the positions from global memory.  Both
-    agree bitwise with the lockstep engine over list updates and
-    exchanges."""
+    exactly, one atom more reads the positions from global memory, where the
+    sums of tpa passes share one epilogue round (the FP64 form's copy sits
+    above the list-build tables: 2432 atoms).  Both agree bitwise with the
+    lockstep engine over list updates and exchanges."""
     N = [nfit, nfit + 1]
     R, Nx = len(N), 10
     T = W.ladder(0.8, 1.3, R)
     out = {}
     for eng in ("lockstep", "persistent"):
         e = relib.Engine(N, T, 0.8442, RC, SKIN, DT, Nx, 5, engine=eng, threads_per_atom=tpa,
-                         watchdog_seconds=10)
+                         precision=precision, watchdog_seconds=10)
         e.step(40)
         out[eng] = ([e.get_state(r) for r in range(R)], e.query_steps()[1].copy(), e.query_energies().copy())
         e.close()
